@@ -1,0 +1,235 @@
+"""Plain FP64 CPU oracle of the explicit electromagnetic PIC step.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and
+the ``cpu_baseline`` leg of ``bench.py`` may import this package.  The
+product library never loads it; it shares no code with the GPU path.
+
+The arithmetic lives in ``pic_oracle.c`` (plain C, FP64, loops in particle
+index order); this module compiles it with gcc and marshals numpy arrays
+through ctypes.  Each C function cites the published method it follows:
+B-spline shapes, Boris (1970), Esirkepov (2001), Yee (1966) -- the four steps
+of the fully-kinetic explicit EM PIC method the paper names in Sec. II and
+Sec. IV.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "pic_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build() -> str:
+    """Compile the oracle (always recompiles)."""
+    cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off",
+           "-fno-fast-math", "-o", _LIB + ".tmp", _SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+class Grid(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("n", C.c_int32 * 3), ("dx", C.c_double * 3),
+                ("dt", C.c_double), ("order", C.c_int32)]
+
+
+class Species(C.Structure):
+    _fields_ = [("np", C.c_int64), ("q", C.c_double), ("m", C.c_double),
+                ("x", C.c_void_p * 3), ("u", C.c_void_p * 3), ("w", C.c_void_p)]
+
+
+_P = C.c_void_p
+_D = C.c_double
+_I = C.c_int32
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build()
+        L = C.CDLL(_LIB)
+        L.orc_shape.argtypes = [_I, _D]
+        L.orc_shape.restype = _D
+        L.orc_gather.argtypes = [C.POINTER(Grid), _P, _P, _P, _P, _P]
+        L.orc_boris.argtypes = [_D, _D, _D, _P, _P, _P]
+        L.orc_deposit.argtypes = [C.POINTER(Grid), _P, _D, _D, _P, _P, _D]
+        L.orc_faraday.argtypes = [C.POINTER(Grid), _P, _P, _D]
+        L.orc_ampere.argtypes = [C.POINTER(Grid), _P, _P, _P, _D]
+        L.orc_fdtd_step.argtypes = [C.POINTER(Grid), _P, _P, _P]
+        L.orc_wrap.argtypes = [_D, _D]
+        L.orc_wrap.restype = _D
+        L.orc_particles_step.argtypes = [C.POINTER(Grid), _P, _P, _P, C.POINTER(Species), _I]
+        L.orc_pic_step.argtypes = [C.POINTER(Grid), _P, _P, _P, C.POINTER(Species), _I]
+        L.orc_rho.argtypes = [C.POINTER(Grid), _P, C.POINTER(Species)]
+        L.orc_div_j.argtypes = [C.POINTER(Grid), _P, _P]
+        L.orc_field_energy.argtypes = [C.POINTER(Grid), _P, _P]
+        L.orc_field_energy.restype = _D
+        L.orc_kinetic_energy.argtypes = [C.POINTER(Species)]
+        L.orc_kinetic_energy.restype = _D
+        L.orc_tile_keys.argtypes = [C.POINTER(Grid), _P, C.POINTER(Species), _P]
+        L.orc_stable_sort.argtypes = [C.c_int64, _P, _I, _P, _P, _P]
+        _lib = L
+    return _lib
+
+
+# ------------------------------------------------------------------ marshalling
+
+def _f64(a):
+    a = np.asarray(a)
+    if a.dtype != np.float64 or not a.flags.c_contiguous:
+        raise TypeError("oracle arrays must be C-contiguous float64")
+    return a
+
+
+def make_grid(dim, n, dx, dt, order) -> Grid:
+    g = Grid()
+    g.dim = int(dim)
+    for d in range(3):
+        g.n[d] = int(n[d])
+        g.dx[d] = float(dx[d])
+    g.dt = float(dt)
+    g.order = int(order)
+    return g
+
+
+class _FieldPtrs:
+    """Keeps three component arrays alive and exposes a ``double*[3]``."""
+
+    def __init__(self, comps):
+        self.comps = [_f64(c) for c in comps]
+        self.arr = (C.c_void_p * 3)(*[c.ctypes.data for c in self.comps])
+
+    @property
+    def ptr(self):
+        return C.cast(self.arr, C.c_void_p)
+
+
+def _species_struct(sp):
+    """``sp`` is any object with q, m, x (3,np), u (3,np), w (np) float64."""
+    s = Species()
+    x = sp.x
+    s.np = int(x.shape[1])
+    s.q = float(sp.q)
+    s.m = float(sp.m)
+    for d in range(3):
+        s.x[d] = _f64(x[d]).ctypes.data
+        s.u[d] = _f64(sp.u[d]).ctypes.data
+    s.w = _f64(sp.w).ctypes.data
+    return s
+
+
+def _rows(a):
+    """View of a (3, N) array as three contiguous rows (no copy)."""
+    a = _f64(a)
+    return [a[0], a[1], a[2]]
+
+
+# ------------------------------------------------------------------ API
+
+def shape(order: int, a: float) -> float:
+    return lib().orc_shape(order, a)
+
+
+def gather(g: Grid, E, B, xi):
+    Ef, Bf = _FieldPtrs(_rows(E)), _FieldPtrs(_rows(B))
+    x = np.ascontiguousarray(xi, dtype=np.float64)
+    Ep = np.zeros(3)
+    Bp = np.zeros(3)
+    lib().orc_gather(C.byref(g), Ef.ptr, Bf.ptr, x.ctypes.data, Ep.ctypes.data, Bp.ctypes.data)
+    return Ep, Bp
+
+
+def boris(q, m, dt, Ep, Bp, u):
+    u = np.array(u, dtype=np.float64)
+    Ep = np.ascontiguousarray(Ep, dtype=np.float64)
+    Bp = np.ascontiguousarray(Bp, dtype=np.float64)
+    lib().orc_boris(q, m, dt, Ep.ctypes.data, Bp.ctypes.data, u.ctypes.data)
+    return u
+
+
+def deposit(g: Grid, J, q, w, x0, x1, vy=0.0):
+    """Adds one particle's Esirkepov current into J (3, N) in place."""
+    Jf = _FieldPtrs(_rows(J))
+    a0 = np.ascontiguousarray(x0, dtype=np.float64)
+    a1 = np.ascontiguousarray(x1, dtype=np.float64)
+    lib().orc_deposit(C.byref(g), Jf.ptr, q, w, a0.ctypes.data, a1.ctypes.data, vy)
+
+
+def faraday(g: Grid, E, B, h):
+    lib().orc_faraday(C.byref(g), _FieldPtrs(_rows(E)).ptr, _FieldPtrs(_rows(B)).ptr, h)
+
+
+def ampere(g: Grid, E, B, J, dt):
+    lib().orc_ampere(C.byref(g), _FieldPtrs(_rows(E)).ptr, _FieldPtrs(_rows(B)).ptr,
+                     _FieldPtrs(_rows(J)).ptr, dt)
+
+
+def fdtd_step(g: Grid, E, B, J):
+    Ef, Bf, Jf = _FieldPtrs(_rows(E)), _FieldPtrs(_rows(B)), _FieldPtrs(_rows(J))
+    lib().orc_fdtd_step(C.byref(g), Ef.ptr, Bf.ptr, Jf.ptr)
+
+
+def wrap(x, L):
+    return lib().orc_wrap(x, L)
+
+
+def particles_step(g: Grid, E, B, J, species):
+    """J is zeroed and filled; species arrays are updated in place."""
+    Ef, Bf, Jf = _FieldPtrs(_rows(E)), _FieldPtrs(_rows(B)), _FieldPtrs(_rows(J))
+    arr = (Species * len(species))(*[_species_struct(s) for s in species])
+    lib().orc_particles_step(C.byref(g), Ef.ptr, Bf.ptr, Jf.ptr, arr, len(species))
+
+
+def pic_step(g: Grid, E, B, J, species):
+    Ef, Bf, Jf = _FieldPtrs(_rows(E)), _FieldPtrs(_rows(B)), _FieldPtrs(_rows(J))
+    arr = (Species * len(species))(*[_species_struct(s) for s in species])
+    lib().orc_pic_step(C.byref(g), Ef.ptr, Bf.ptr, Jf.ptr, arr, len(species))
+
+
+def rho(g: Grid, species, ncells):
+    out = np.zeros(ncells)
+    for s in species:
+        st = _species_struct(s)
+        lib().orc_rho(C.byref(g), out.ctypes.data, C.byref(st))
+    return out
+
+
+def div_j(g: Grid, J, ncells):
+    out = np.zeros(ncells)
+    lib().orc_div_j(C.byref(g), _FieldPtrs(_rows(J)).ptr, out.ctypes.data)
+    return out
+
+
+def field_energy(g: Grid, E, B):
+    return lib().orc_field_energy(C.byref(g), _FieldPtrs(_rows(E)).ptr, _FieldPtrs(_rows(B)).ptr)
+
+
+def kinetic_energy(sp):
+    st = _species_struct(sp)
+    return lib().orc_kinetic_energy(C.byref(st))
+
+
+def tile_keys(g: Grid, tile, sp):
+    st = _species_struct(sp)
+    t = np.ascontiguousarray(tile, dtype=np.int32)
+    key = np.zeros(st.np, dtype=np.int32)
+    lib().orc_tile_keys(C.byref(g), t.ctypes.data, C.byref(st), key.ctypes.data)
+    return key
+
+
+def stable_sort(key, nkeys):
+    key = np.ascontiguousarray(key, dtype=np.int32)
+    n = key.shape[0]
+    perm = np.zeros(n, dtype=np.int32)
+    count = np.zeros(nkeys, dtype=np.int32)
+    offset = np.zeros(nkeys + 1, dtype=np.int32)
+    lib().orc_stable_sort(n, key.ctypes.data, nkeys, perm.ctypes.data,
+                          count.ctypes.data, offset.ctypes.data)
+    return perm, count, offset
