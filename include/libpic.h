@@ -1,0 +1,192 @@
+/*
+ * libpic -- MI355X (gfx950) hot path of an explicit electromagnetic
+ * particle-in-cell step: shape-factor field gather, relativistic Boris push,
+ * charge-conserving (Esirkepov) current deposition and the Yee FDTD update,
+ * plus the per-tile particle sort that keeps the LDS-tiled kernels fed.
+ *
+ * The paper (Sec. II) places its code among "fully-kinetic, electromagnetic
+ * particle-in-cell" models, explicit in time t, and (Sec. III.A) measures it
+ * by the rate of particle and cell updates per second; the operations below
+ * are the four steps of such a time step, as defined by the published
+ * methods: B-spline shapes, Boris (1970), Esirkepov (Comput. Phys. Commun.
+ * 135, 2001) and Yee (IEEE TAP 14, 1966).
+ *
+ * Conventions (every entry point)
+ *   - Normalised units: c = eps0 = mu0 = 1.  u = gamma v.
+ *   - Particle positions are in CELL units of their box, in [0, n_d).
+ *   - Fields of a box are periodic Yee arrays stored x-fastest, index
+ *     i + n0*(j + n1*k):  Ex(i+1/2,j,k) Ey(i,j+1/2,k) Ez(i,j,k+1/2),
+ *     Bx(i,j+1/2,k+1/2) By(i+1/2,j,k+1/2) Bz(i+1/2,j+1/2,k); J with E.
+ *     Several boxes share one allocation per component: box b occupies
+ *     cells [cell_base, cell_base + n0*n1*n2).
+ *   - dim == 2 is the x-z plane: n[1] == 1, tile[1] == 1, d/dy == 0, all
+ *     three velocity and six field components kept.
+ *   - Every pointer inside pic_fields / pic_species is a DEVICE pointer
+ *     owned by the caller; the library keeps none of them past the call
+ *     (except inside a captured step graph, see pic_step).
+ *   - All work is enqueued on the stream given to pic_init; calls return
+ *     before the GPU finishes.  Host-detectable errors are returned before
+ *     any launch; device-side range errors are latched in a flag that
+ *     pic_check reports.  Nothing throws across this interface.
+ *   - A context is not thread-safe; use one per stream.
+ */
+#ifndef LIBPIC_H
+#define LIBPIC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PIC_OK = 0,
+    PIC_ERR_ARG = 1,     /* bad argument (null pointer, bad size, order, dims) */
+    PIC_ERR_CFL = 2,     /* dt above the Courant limit of the box */
+    PIC_ERR_OOM = 3,     /* device allocation failed */
+    PIC_ERR_DEVICE = 4,  /* a HIP runtime call failed */
+    PIC_ERR_RANGE = 5,   /* device flag: a position outside its box, a per-step
+                            displacement of 0.999 cell or more, or a
+                            non-finite value; such a particle is left in
+                            place and deposits nothing */
+    PIC_ERR_STATE = 6    /* call order violated (e.g. deposit without a push,
+                            tiled kernel before any sort) */
+} pic_status;
+
+typedef enum {
+    PIC_FP64 = 0,        /* FP64 positions, momenta, weights, fields */
+    PIC_FP32_SPLIT = 1   /* int32 cell + FP32 offset positions; FP32 momenta,
+                            weights, E and B; FP64 J */
+} pic_precision;
+
+typedef enum {
+    PIC_KERNEL_DIRECT = 0,  /* one thread per particle, fields and J in global
+                               memory (no sort needed) */
+    PIC_KERNEL_TILED = 1,   /* one workgroup per (species, tile): E/B staged
+                               in LDS, J accumulated in LDS then flushed with
+                               FP64 global atomics (needs pic_sort_tiles) */
+    PIC_KERNEL_BATCHED = 2  /* as TILED, but a persistent grid walks a work
+                               queue of (species, tile, chunk) items so uneven
+                               tiles and many boxes share one launch */
+} pic_kernel;
+
+typedef struct {
+    int32_t dim;         /* 2 or 3 */
+    int32_t n[3];        /* cells per axis, each >= 1 and < 2^20 */
+    double dx[3];        /* cell size per axis (> 0) */
+    double dt;           /* time step; must satisfy the Courant limit */
+    int32_t order;       /* B-spline order 1..3 */
+    int32_t tile[3];     /* tile edge per axis for the sort and the tiled
+                            kernels (1..16; partial tiles at the high end) */
+    int64_t cell_base;   /* offset of this box in the field arrays */
+} pic_box_desc;
+
+typedef struct {
+    int32_t kernel;      /* pic_kernel */
+    int32_t block;       /* threads per workgroup of particle kernels
+                            (64..512, multiple of 64; 0 = default 256) */
+    int32_t chunk;       /* BATCHED: max particles per work item (0 = 4096) */
+    int32_t wg_per_cu;   /* BATCHED: persistent workgroups per CU (0 = 2) */
+} pic_tuning;
+
+typedef struct {
+    void *E[3];          /* FP64 (PIC_FP64) or FP32 (PIC_FP32_SPLIT) */
+    void *B[3];
+    double *J[3];        /* FP64 in both precisions */
+} pic_fields;
+
+typedef struct {
+    int64_t np;          /* particles (0 allowed; < 2^31) */
+    double q, m;         /* charge and mass of one physical particle */
+    int32_t box;         /* index into the box list given to pic_init */
+    double *x[3];        /* PIC_FP64: positions; x[1] unused in 2D */
+    int32_t *cell;       /* PIC_FP32_SPLIT: linear cell id within the box */
+    float *off[3];       /* PIC_FP32_SPLIT: in-cell offsets in [0, 1);
+                            off[1] unused in 2D */
+    void *u[3];          /* momenta, FP64 or FP32 per precision */
+    void *w;             /* weights, FP64 or FP32 per precision */
+} pic_species;
+
+typedef struct pic_ctx pic_ctx;
+
+/* Create a context for nboxes boxes at the given precision, bound to
+ * `stream` (a hipStream_t; NULL = the null stream).  Validates every box
+ * (dims, order, tile, Courant limit dt <= 1/sqrt(sum 1/dx_d^2) over the
+ * box's axes) and allocates the context's own scratch (device error flag,
+ * tile tables).  `tuning` may be NULL (defaults: BATCHED for FP32_SPLIT,
+ * TILED for FP64).  On error *ctx is NULL. */
+pic_status pic_init(pic_ctx **ctx, const pic_box_desc *boxes, int32_t nboxes,
+                    pic_precision prec, void *stream, const pic_tuning *tuning);
+
+/* Per-tile stable counting sort (least-significant-digit radix passes over
+ * the tile id): every species' particle arrays are permuted IN PLACE so that
+ * particles are grouped by tile id = tx + ntx*(ty + nty*tz) of their cell,
+ * ties kept in their previous order.  The per-tile offsets are kept in the
+ * context for the tiled kernels.  Optional outputs, each an array of nsp
+ * device pointers (the array itself on the host; it or any entry may be
+ * NULL): perm_out[s][i] = previous index of the particle now at i;
+ * key_out[s][i] = its tile id; tile_offset_out[s] = ntiles+1 exclusive
+ * offsets.  Species must be passed in the same order to every call. */
+pic_status pic_sort_tiles(pic_ctx *ctx, const pic_species *sp, int32_t nsp,
+                          int32_t *const *perm_out, int32_t *const *key_out,
+                          int32_t *const *tile_offset_out);
+
+/* Gather E, B at x^n with order-n shapes (each component on its own Yee
+ * points), Boris-push u^(n-1/2) -> u^(n+1/2), advance positions to x^(n+1).
+ * x^n is kept in context scratch for pic_deposit_J.  Until that call FP64
+ * positions are left unwrapped (within one cell outside [0, n)); split
+ * positions are stored wrapped, their cell change kept in scratch. */
+pic_status pic_gather_push(pic_ctx *ctx, const pic_fields *f, pic_species *sp,
+                           int32_t nsp);
+
+/* Zero J of every box, deposit the Esirkepov current of the move
+ * x^n -> x^(n+1) recorded by the last pic_gather_push, then wrap positions
+ * periodically.  PIC_ERR_STATE without a preceding pic_gather_push on the
+ * same species. */
+pic_status pic_deposit_J(pic_ctx *ctx, pic_fields *f, pic_species *sp,
+                         int32_t nsp);
+
+/* Fused form of pic_gather_push + pic_deposit_J in one kernel pass:
+ * zero J, then gather, push, advance, deposit, wrap. */
+pic_status pic_advance(pic_ctx *ctx, pic_fields *f, pic_species *sp,
+                       int32_t nsp);
+
+/* Yee update of every box: B -= (dt/2) curl E; E += dt (curl B - J);
+ * B -= (dt/2) curl E.  Periodic. */
+pic_status pic_fdtd_step(pic_ctx *ctx, pic_fields *f);
+
+/* One whole step (optional sort, pic_advance, pic_fdtd_step) recorded once
+ * into a HIP graph per distinct (fields, species, sort) binding and
+ * replayed with a single graph launch afterwards.  The caller must keep the
+ * bound arrays alive while the context may replay the graph. */
+pic_status pic_step(pic_ctx *ctx, pic_fields *f, pic_species *sp, int32_t nsp,
+                    int32_t sort);
+
+/* Charge density rho = sum q w S S S / dV on the nodes of box `box`, FP64,
+ * ADDED into rho (ncells of that box).  A check, not part of the step. */
+pic_status pic_deposit_rho(pic_ctx *ctx, const pic_species *sp, int32_t nsp,
+                           int32_t box, double *rho);
+
+/* Node divergence of an E-staggered vector field (J or E, FP64) of box
+ * `box` into out (ncells).  A check, not part of the step. */
+pic_status pic_div_edge(pic_ctx *ctx, int32_t box, double *const v[3],
+                        double *out);
+
+/* Wait for the stream and report the first device-side error (then clear). */
+pic_status pic_check(pic_ctx *ctx);
+
+/* Release the context and its scratch (waits for the stream). NULL is OK. */
+pic_status pic_free(pic_ctx *ctx);
+
+/* Static text for a status; and the message of the last failed call. */
+const char *pic_status_str(pic_status s);
+const char *pic_last_error(void);
+
+/* Number of workgroups the context's kernels fill the device with (CUs). */
+int32_t pic_device_cus(pic_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif

@@ -1,0 +1,783 @@
+// libpic host runtime: the C ABI declared in include/libpic.h.  Validates
+// arguments on the host, owns the context's device scratch (error flag, box
+// and species tables, sort buffers, work-item queue, per-species x^n
+// scratch), enqueues every kernel on the context's stream, and records
+// whole steps into HIP graphs.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/libpic.h"
+#include "pic_aux.h"
+#include "pic_dev.h"
+#include "pic_math.h"
+
+using namespace pic;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+pic_status fail(pic_status s, const std::string &msg) {
+    g_last_error = msg;
+    return s;
+}
+
+#define HIP_TRY(expr)                                                                 \
+    do {                                                                              \
+        hipError_t e_ = (expr);                                                       \
+        if (e_ != hipSuccess)                                                         \
+            return fail(PIC_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr int LDS_BYTES_MAX = 160 * 1024 - 256;   // leave room for static LDS
+
+int halo_gl(int o) { return o == 1 ? 1 : (o == 2 ? 1 : 2); }
+int halo_gh(int o) { return o == 1 ? 1 : 2; }
+int halo_jl(int o) { return o == 1 ? 1 : 2; }
+int halo_jh(int o) { return o == 1 ? 2 : 3; }
+
+struct Slot {
+    long long cap = 0;          // particles the scratch below can hold
+    int prec_bytes = 0;
+    double *xo[3] = {nullptr, nullptr, nullptr};
+    int *cello = nullptr;
+    float *offo[3] = {nullptr, nullptr, nullptr};
+    int *carry = nullptr;
+    int *tile_off = nullptr;
+    int tile_cap = 0;
+    // state of the last binding
+    const void *key_ptr = nullptr;
+    long long np = -1;
+    int box = -1;
+    bool sorted = false;
+    bool pushed = false;
+};
+
+template <typename T> pic_status dalloc(T **p, size_t n) {
+    *p = nullptr;
+    if (n == 0) n = 1;
+    hipError_t e = hipMalloc((void **)p, n * sizeof(T));
+    if (e != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return fail(PIC_ERR_OOM, "hipMalloc of " + std::to_string(n * sizeof(T)) + " bytes failed");
+    }
+    return PIC_OK;
+}
+
+template <typename T> void dfree(T *&p) {
+    if (p) (void)hipFree((void *)p);
+    p = nullptr;
+}
+
+}  // namespace
+
+struct pic_ctx {
+    int nboxes = 0;
+    int order = 1;
+    pic_precision prec = PIC_FP64;
+    hipStream_t stream = nullptr;
+    pic_tuning tun{};
+    int cus = 256;
+    std::vector<DevBox> hbox;
+    DevBox *dbox = nullptr;
+    std::vector<long long> hfp;     // flat cell prefix over boxes
+    long long *dfp = nullptr;
+    long long total_cells = 0;
+    int *derr = nullptr;
+    size_t lds_field_bytes = 0, lds_bytes = 0;
+    // species
+    std::vector<Slot> slots;
+    std::vector<DevSpecies> hsp;    // last uploaded table
+    DevSpecies *dsp = nullptr;
+    int dsp_cap = 0;
+    std::vector<int> hprefix;
+    int *dprefix = nullptr;
+    int nslots = 0;
+    // sort scratch
+    long long sort_cap = 0;
+    int *keys[2] = {nullptr, nullptr};
+    int *vals[2] = {nullptr, nullptr};
+    void *tmp = nullptr;
+    int *counts = nullptr;
+    int *scan_scr = nullptr;
+    size_t counts_cap = 0, scan_cap = 0;
+    // batched work items
+    Item *items = nullptr;
+    long long items_cap = 0;
+    int *item_counts = nullptr, *item_starts = nullptr;
+    int item_slot_cap = 0;
+    int *nitems = nullptr, *queue = nullptr;
+    // graphs
+    std::map<std::string, hipGraphExec_t> graphs;
+    bool capturing = false;
+    hipStream_t cap_stream = nullptr;   // private stream graphs are recorded on
+};
+
+namespace {
+
+int key_bits(int nkeys) {
+    int b = 0;
+    while ((1ll << b) < (long long)nkeys) ++b;
+    return b < 1 ? 1 : b;
+}
+
+pic_status check_box(const pic_box_desc &b, int i) {
+    std::string w = "box " + std::to_string(i) + ": ";
+    if (b.dim != 2 && b.dim != 3) return fail(PIC_ERR_ARG, w + "dim must be 2 or 3");
+    if (b.order < 1 || b.order > 3) return fail(PIC_ERR_ARG, w + "order must be 1..3");
+    long long nc = 1;
+    for (int d = 0; d < 3; ++d) {
+        if (b.n[d] < 1 || b.n[d] >= (1 << 20)) return fail(PIC_ERR_ARG, w + "n out of range");
+        if (b.tile[d] < 1 || b.tile[d] > 16) return fail(PIC_ERR_ARG, w + "tile must be 1..16");
+        if (!(b.dx[d] > 0.0) || !std::isfinite(b.dx[d])) return fail(PIC_ERR_ARG, w + "dx must be > 0");
+        nc *= b.n[d];
+    }
+    if (nc >= (1ll << 31)) return fail(PIC_ERR_ARG, w + "more than 2^31-1 cells");
+    if (b.dim == 2 && (b.n[1] != 1 || b.tile[1] != 1))
+        return fail(PIC_ERR_ARG, w + "2D boxes need n[1] == 1 and tile[1] == 1");
+    if (!(b.dt > 0.0) || !std::isfinite(b.dt)) return fail(PIC_ERR_ARG, w + "dt must be > 0");
+    if (b.cell_base < 0) return fail(PIC_ERR_ARG, w + "cell_base < 0");
+    double s = 0.0;
+    for (int d = 0; d < 3; ++d) {
+        if (b.dim == 2 && d == 1) continue;
+        s += 1.0 / (b.dx[d] * b.dx[d]);
+    }
+    if (b.dt * std::sqrt(s) > 1.0 + 1e-12)
+        return fail(PIC_ERR_CFL, w + "dt above the Courant limit 1/sqrt(sum 1/dx^2)");
+    return PIC_OK;
+}
+
+pic_status ensure_slot_scratch(pic_ctx *c, Slot &sl, long long np) {
+    const int pb = c->prec == PIC_FP64 ? 8 : 4;
+    if (sl.cap >= np && sl.prec_bytes == pb) return PIC_OK;
+    for (int d = 0; d < 3; ++d) { dfree(sl.xo[d]); dfree(sl.offo[d]); }
+    dfree(sl.cello);
+    dfree(sl.carry);
+    pic_status s;
+    if (c->prec == PIC_FP64) {
+        for (int d = 0; d < 3; ++d)
+            if ((s = dalloc(&sl.xo[d], (size_t)np)) != PIC_OK) return s;
+    } else {
+        for (int d = 0; d < 3; ++d)
+            if ((s = dalloc(&sl.offo[d], (size_t)np)) != PIC_OK) return s;
+        if ((s = dalloc(&sl.cello, (size_t)np)) != PIC_OK) return s;
+        if ((s = dalloc(&sl.carry, (size_t)np)) != PIC_OK) return s;
+    }
+    sl.cap = np;
+    sl.prec_bytes = pb;
+    return PIC_OK;
+}
+
+pic_status validate_species(pic_ctx *c, const pic_species *sp, int nsp) {
+    if (nsp < 0) return fail(PIC_ERR_ARG, "nsp < 0");
+    if (nsp > 0 && !sp) return fail(PIC_ERR_ARG, "species array is NULL");
+    for (int s = 0; s < nsp; ++s) {
+        const pic_species &p = sp[s];
+        std::string w = "species " + std::to_string(s) + ": ";
+        if (p.box < 0 || p.box >= c->nboxes) return fail(PIC_ERR_ARG, w + "box index out of range");
+        if (p.np < 0 || p.np >= (1ll << 31)) return fail(PIC_ERR_ARG, w + "np out of range");
+        if (!(p.m > 0.0) || !std::isfinite(p.q) || !std::isfinite(p.m))
+            return fail(PIC_ERR_ARG, w + "bad q or m");
+        if (p.np == 0) continue;
+        const bool two = c->hbox[p.box].dim == 2;
+        for (int d = 0; d < 3; ++d)
+            if (!p.u[d]) return fail(PIC_ERR_ARG, w + "u pointer is NULL");
+        if (!p.w) return fail(PIC_ERR_ARG, w + "w pointer is NULL");
+        if (c->prec == PIC_FP64) {
+            for (int d = 0; d < 3; ++d)
+                if (!(two && d == 1) && !p.x[d]) return fail(PIC_ERR_ARG, w + "x pointer is NULL");
+        } else {
+            if (!p.cell) return fail(PIC_ERR_ARG, w + "cell pointer is NULL");
+            for (int d = 0; d < 3; ++d)
+                if (!(two && d == 1) && !p.off[d]) return fail(PIC_ERR_ARG, w + "off pointer is NULL");
+        }
+    }
+    return PIC_OK;
+}
+
+// Upload the species table when the binding changed; (re)size per-species
+// scratch.  need_push_scratch: also allocate the x^n scratch.
+pic_status bind_species(pic_ctx *c, const pic_species *sp, int nsp, bool need_push_scratch) {
+    pic_status st = validate_species(c, sp, nsp);
+    if (st != PIC_OK) return st;
+    if ((int)c->slots.size() < nsp) c->slots.resize(nsp);
+    std::vector<DevSpecies> t(nsp);
+    std::vector<int> prefix(nsp + 1, 0);
+    bool realloc_happened = false;
+    for (int s = 0; s < nsp; ++s) {
+        const pic_species &p = sp[s];
+        Slot &sl = c->slots[s];
+        const DevBox &b = c->hbox[p.box];
+        const void *kp = c->prec == PIC_FP64 ? (const void *)p.x[0] : (const void *)p.cell;
+        if (sl.key_ptr != kp || sl.np != p.np || sl.box != p.box) {
+            sl.sorted = false;
+            sl.pushed = false;
+        }
+        sl.key_ptr = kp;
+        sl.np = p.np;
+        sl.box = p.box;
+        if (need_push_scratch && sl.cap < p.np) {
+            if (c->capturing) return fail(PIC_ERR_STATE, "scratch growth during graph capture");
+            (void)hipStreamSynchronize(c->stream);
+            if ((st = ensure_slot_scratch(c, sl, p.np)) != PIC_OK) return st;
+            realloc_happened = true;
+        }
+        if (sl.tile_cap < b.ntiles + 2) {
+            if (c->capturing) return fail(PIC_ERR_STATE, "scratch growth during graph capture");
+            (void)hipStreamSynchronize(c->stream);
+            dfree(sl.tile_off);
+            if ((st = dalloc(&sl.tile_off, (size_t)b.ntiles + 2)) != PIC_OK) return st;
+            sl.tile_cap = b.ntiles + 2;
+            sl.sorted = false;
+            realloc_happened = true;
+        }
+        DevSpecies &d = t[s];
+        std::memset(&d, 0, sizeof(d));
+        d.np = p.np;
+        d.q = p.q;
+        d.m = p.m;
+        d.box = p.box;
+        d.tile_base = prefix[s];
+        for (int k = 0; k < 3; ++k) {
+            d.x[k] = p.x[k];
+            d.off[k] = p.off[k];
+            d.u[k] = p.u[k];
+            d.xo[k] = sl.xo[k];
+            d.offo[k] = sl.offo[k];
+        }
+        d.cell = p.cell;
+        d.w = p.w;
+        d.cello = sl.cello;
+        d.carry = sl.carry;
+        d.tile_off = sl.tile_off;
+        prefix[s + 1] = prefix[s] + b.ntiles;
+    }
+    (void)realloc_happened;
+    bool same = (int)c->hsp.size() == nsp &&
+                (nsp == 0 || std::memcmp(c->hsp.data(), t.data(), nsp * sizeof(DevSpecies)) == 0);
+    if (!same) {
+        if (c->capturing) return fail(PIC_ERR_STATE, "species binding changed during graph capture");
+        (void)hipStreamSynchronize(c->stream);
+        if (c->dsp_cap < nsp + 1) {
+            dfree(c->dsp);
+            dfree(c->dprefix);
+            int cap = nsp + 8;
+            if ((st = dalloc(&c->dsp, (size_t)cap)) != PIC_OK) return st;
+            if ((st = dalloc(&c->dprefix, (size_t)cap + 1)) != PIC_OK) return st;
+            c->dsp_cap = cap;
+        }
+        if (nsp > 0) {
+            HIP_TRY(hipMemcpy(c->dsp, t.data(), nsp * sizeof(DevSpecies), hipMemcpyHostToDevice));
+        }
+        HIP_TRY(hipMemcpy(c->dprefix, prefix.data(), (nsp + 1) * sizeof(int), hipMemcpyHostToDevice));
+        c->hsp = t;
+        c->hprefix = prefix;
+    }
+    c->nslots = prefix[nsp];
+    return PIC_OK;
+}
+
+KParams make_params(pic_ctx *c, const pic_fields *f, int nsp) {
+    KParams k;
+    std::memset(&k, 0, sizeof(k));
+    k.boxes = c->dbox;
+    k.species = c->dsp;
+    k.nsp = nsp;
+    if (f) {
+        for (int d = 0; d < 3; ++d) {
+            k.f.E[d] = f->E[d];
+            k.f.B[d] = f->B[d];
+            k.f.J[d] = f->J[d];
+        }
+    }
+    k.err = c->derr;
+    k.sp_tile_prefix = c->dprefix;
+    k.items = c->items;
+    k.nitems = c->nitems;
+    k.queue = c->queue;
+    k.lds_field_bytes = (int)c->lds_field_bytes;
+    return k;
+}
+
+hipError_t launch_particles(pic_ctx *c, const KParams &k, int form, int mode, int grid,
+                            int species) {
+    const int prec = c->prec == PIC_FP64 ? 0 : 1;
+    const int block = c->tun.block;
+    switch (c->order) {
+        case 1: return launch_particles_o1(k, prec, form, mode, grid, block, c->lds_bytes, species, c->stream);
+        case 2: return launch_particles_o2(k, prec, form, mode, grid, block, c->lds_bytes, species, c->stream);
+        default: return launch_particles_o3(k, prec, form, mode, grid, block, c->lds_bytes, species, c->stream);
+    }
+}
+
+pic_status check_fields(pic_ctx *c, const pic_fields *f, bool need_eb) {
+    if (!f) return fail(PIC_ERR_ARG, "fields is NULL");
+    for (int d = 0; d < 3; ++d) {
+        if (!f->J[d]) return fail(PIC_ERR_ARG, "J pointer is NULL");
+        if (need_eb && (!f->E[d] || !f->B[d])) return fail(PIC_ERR_ARG, "E/B pointer is NULL");
+    }
+    (void)c;
+    return PIC_OK;
+}
+
+pic_status run_particles(pic_ctx *c, pic_fields *f, pic_species *sp, int nsp, int mode) {
+    if (!c) return fail(PIC_ERR_ARG, "ctx is NULL");
+    pic_status st = check_fields(c, f, (mode & MODE_PUSH) != 0);
+    if (st != PIC_OK) return st;
+    if ((st = bind_species(c, sp, nsp, mode == MODE_PUSH || mode == MODE_DEPOSIT)) != PIC_OK) return st;
+    const int form = c->tun.kernel;
+    for (int s = 0; s < nsp; ++s) {
+        Slot &sl = c->slots[s];
+        if (form != PIC_KERNEL_DIRECT && !sl.sorted && sp[s].np > 0)
+            return fail(PIC_ERR_STATE, "tiled kernels need pic_sort_tiles first (species " +
+                                           std::to_string(s) + ")");
+        if (mode == MODE_DEPOSIT && !sl.pushed && sp[s].np > 0)
+            return fail(PIC_ERR_STATE, "pic_deposit_J without a preceding pic_gather_push");
+    }
+    KParams k = make_params(c, f, nsp);
+    if (mode & MODE_DEPOSIT)
+        HIP_TRY(launch_zero_j(k.f, c->dbox, c->dfp, c->nboxes, c->total_cells, c->stream));
+    if (form == PIC_KERNEL_DIRECT) {
+        for (int s = 0; s < nsp; ++s) {
+            if (sp[s].np == 0) continue;
+            int grid = (int)((sp[s].np + 255) / 256);
+            HIP_TRY(launch_particles(c, k, 0, mode, grid, s));
+        }
+    } else if (form == PIC_KERNEL_TILED) {
+        if (c->nslots > 0) HIP_TRY(launch_particles(c, k, 1, mode, c->nslots, 0));
+    } else {
+        HIP_TRY(launch_set_int(c->queue, 0, c->stream));
+        int grid = c->cus * c->tun.wg_per_cu;
+        HIP_TRY(launch_particles(c, k, 2, mode, grid, 0));
+    }
+    for (int s = 0; s < nsp; ++s) {
+        if (mode == MODE_PUSH) c->slots[s].pushed = true;
+        else c->slots[s].pushed = false;
+    }
+    return PIC_OK;
+}
+
+pic_status ensure_sort_scratch(pic_ctx *c, long long np, long long nitems_cap) {
+    pic_status st;
+    if (c->sort_cap < np) {
+        if (c->capturing) return fail(PIC_ERR_STATE, "scratch growth during graph capture");
+        (void)hipStreamSynchronize(c->stream);
+        for (int i = 0; i < 2; ++i) { dfree(c->keys[i]); dfree(c->vals[i]); }
+        if (c->tmp) { (void)hipFree(c->tmp); c->tmp = nullptr; }
+        for (int i = 0; i < 2; ++i) {
+            if ((st = dalloc(&c->keys[i], (size_t)np)) != PIC_OK) return st;
+            if ((st = dalloc(&c->vals[i], (size_t)np)) != PIC_OK) return st;
+        }
+        if (hipMalloc(&c->tmp, (size_t)std::max<long long>(np, 1) * 8) != hipSuccess) {
+            c->tmp = nullptr;
+            return fail(PIC_ERR_OOM, "sort buffer allocation failed");
+        }
+        c->sort_cap = np;
+    }
+    size_t need_counts = (size_t)radix_blocks(np) * 256 + 256;
+    size_t need_scan = std::max(scan_scratch_ints((long long)need_counts),
+                                scan_scratch_ints((long long)c->nslots + 1));
+    if (c->counts_cap < need_counts) {
+        if (c->capturing) return fail(PIC_ERR_STATE, "scratch growth during graph capture");
+        (void)hipStreamSynchronize(c->stream);
+        dfree(c->counts);
+        if ((st = dalloc(&c->counts, need_counts)) != PIC_OK) return st;
+        c->counts_cap = need_counts;
+    }
+    if (c->scan_cap < need_scan) {
+        if (c->capturing) return fail(PIC_ERR_STATE, "scratch growth during graph capture");
+        (void)hipStreamSynchronize(c->stream);
+        dfree(c->scan_scr);
+        if ((st = dalloc(&c->scan_scr, need_scan)) != PIC_OK) return st;
+        c->scan_cap = need_scan;
+    }
+    if (c->tun.kernel == PIC_KERNEL_BATCHED) {
+        if (c->item_slot_cap < c->nslots + 1) {
+            if (c->capturing) return fail(PIC_ERR_STATE, "scratch growth during graph capture");
+            (void)hipStreamSynchronize(c->stream);
+            dfree(c->item_counts);
+            dfree(c->item_starts);
+            int cap = c->nslots + 64;
+            if ((st = dalloc(&c->item_counts, (size_t)cap)) != PIC_OK) return st;
+            if ((st = dalloc(&c->item_starts, (size_t)cap)) != PIC_OK) return st;
+            c->item_slot_cap = cap;
+        }
+        if (c->items_cap < nitems_cap) {
+            if (c->capturing) return fail(PIC_ERR_STATE, "scratch growth during graph capture");
+            (void)hipStreamSynchronize(c->stream);
+            dfree(c->items);
+            if ((st = dalloc(&c->items, (size_t)nitems_cap)) != PIC_OK) return st;
+            c->items_cap = nitems_cap;
+        }
+    }
+    return PIC_OK;
+}
+
+pic_status do_sort(pic_ctx *c, const pic_species *sp, int nsp, int32_t *const *perm_out,
+                   int32_t *const *key_out, int32_t *const *off_out) {
+    if (!c) return fail(PIC_ERR_ARG, "ctx is NULL");
+    pic_status st = bind_species(c, sp, nsp, false);
+    if (st != PIC_OK) return st;
+    long long maxnp = 0, nitems_cap = c->nslots + 1;
+    for (int s = 0; s < nsp; ++s) {
+        if (c->slots[s].pushed) return fail(PIC_ERR_STATE, "sort between pic_gather_push and pic_deposit_J");
+        maxnp = std::max(maxnp, (long long)sp[s].np);
+        nitems_cap += (sp[s].np + c->tun.chunk - 1) / c->tun.chunk;
+    }
+    if ((st = ensure_sort_scratch(c, maxnp, nitems_cap)) != PIC_OK) return st;
+    const int prec = c->prec == PIC_FP64 ? 0 : 1;
+    hipStream_t S = c->stream;
+    for (int s = 0; s < nsp; ++s) {
+        const pic_species &p = sp[s];
+        const DevBox &b = c->hbox[p.box];
+        const long long np = p.np;
+        const int nkeys = b.ntiles + 1;
+        Slot &sl = c->slots[s];
+        HIP_TRY(launch_tile_keys(prec, c->dsp, s, np, c->dbox, c->keys[0], c->vals[0], c->derr, S));
+        const int passes = (key_bits(nkeys) + 7) / 8;
+        int cur = 0;
+        for (int ps = 0; ps < passes; ++ps) {
+            HIP_TRY(radix_pass(c->keys[cur], c->vals[cur], c->keys[1 - cur], c->vals[1 - cur], np,
+                               8 * ps, c->counts, c->scan_scr, S));
+            cur = 1 - cur;
+        }
+        const int *perm = c->vals[cur];
+        HIP_TRY(launch_tile_offsets(c->keys[cur], np, nkeys, sl.tile_off, S));
+        // permute the particle arrays in place through the tmp buffer
+        auto perm8 = [&](void *a) -> hipError_t {
+            hipError_t e = launch_gather8(a, perm, c->tmp, np, S);
+            if (e != hipSuccess) return e;
+            return launch_copy8(c->tmp, a, np, S);
+        };
+        auto perm4 = [&](void *a) -> hipError_t {
+            hipError_t e = launch_gather4(a, perm, c->tmp, np, S);
+            if (e != hipSuccess) return e;
+            return launch_copy4(c->tmp, a, np, S);
+        };
+        const bool two = b.dim == 2;
+        if (np > 0) {
+            if (c->prec == PIC_FP64) {
+                for (int d = 0; d < 3; ++d) {
+                    if (!(two && d == 1)) HIP_TRY(perm8(p.x[d]));
+                    HIP_TRY(perm8(p.u[d]));
+                }
+                HIP_TRY(perm8(p.w));
+            } else {
+                HIP_TRY(perm4(p.cell));
+                for (int d = 0; d < 3; ++d) {
+                    if (!(two && d == 1)) HIP_TRY(perm4(p.off[d]));
+                    HIP_TRY(perm4(p.u[d]));
+                }
+                HIP_TRY(perm4(p.w));
+            }
+        }
+        if (perm_out && perm_out[s]) HIP_TRY(launch_copy4(perm, perm_out[s], np, S));
+        if (key_out && key_out[s]) HIP_TRY(launch_copy4(c->keys[cur], key_out[s], np, S));
+        if (off_out && off_out[s]) HIP_TRY(launch_copy4(sl.tile_off, off_out[s], b.ntiles + 1, S));
+        sl.sorted = true;
+    }
+    if (c->tun.kernel == PIC_KERNEL_BATCHED && c->nslots > 0) {
+        HIP_TRY(launch_items(c->dsp, c->dprefix, nsp, c->nslots, c->tun.chunk, c->item_counts,
+                             c->item_starts, c->scan_scr, c->items, c->nitems, c->queue, S));
+    }
+    return PIC_OK;
+}
+
+pic_status do_fdtd(pic_ctx *c, pic_fields *f) {
+    if (!c) return fail(PIC_ERR_ARG, "ctx is NULL");
+    pic_status st = check_fields(c, f, true);
+    if (st != PIC_OK) return st;
+    KParams k = make_params(c, f, 0);
+    HIP_TRY(launch_fdtd(c->prec == PIC_FP64 ? 0 : 1, k.f, c->dbox, c->dfp, c->nboxes,
+                        c->total_cells, c->stream));
+    return PIC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *pic_status_str(pic_status s) {
+    switch (s) {
+        case PIC_OK: return "ok";
+        case PIC_ERR_ARG: return "invalid argument";
+        case PIC_ERR_CFL: return "time step above the Courant limit";
+        case PIC_ERR_OOM: return "device out of memory";
+        case PIC_ERR_DEVICE: return "HIP runtime error";
+        case PIC_ERR_RANGE: return "particle displacement >= 1 cell, or non-finite value";
+        case PIC_ERR_STATE: return "call order violated";
+    }
+    return "unknown status";
+}
+
+const char *pic_last_error(void) { return g_last_error.c_str(); }
+
+pic_status pic_init(pic_ctx **out, const pic_box_desc *boxes, int32_t nboxes, pic_precision prec,
+                    void *stream, const pic_tuning *tuning) {
+    if (!out) return fail(PIC_ERR_ARG, "ctx out-pointer is NULL");
+    *out = nullptr;
+    if (!boxes || nboxes < 1) return fail(PIC_ERR_ARG, "need at least one box");
+    if (prec != PIC_FP64 && prec != PIC_FP32_SPLIT) return fail(PIC_ERR_ARG, "bad precision");
+    pic_status st;
+    for (int i = 0; i < nboxes; ++i)
+        if ((st = check_box(boxes[i], i)) != PIC_OK) return st;
+    for (int i = 1; i < nboxes; ++i)
+        if (boxes[i].order != boxes[0].order)
+            return fail(PIC_ERR_ARG, "all boxes of a context must share one shape order");
+    pic_tuning t{};
+    t.kernel = prec == PIC_FP64 ? PIC_KERNEL_TILED : PIC_KERNEL_BATCHED;
+    t.block = 256;
+    t.chunk = 4096;
+    t.wg_per_cu = 2;
+    if (tuning) {
+        t.kernel = tuning->kernel;
+        if (tuning->block) t.block = tuning->block;
+        if (tuning->chunk) t.chunk = tuning->chunk;
+        if (tuning->wg_per_cu) t.wg_per_cu = tuning->wg_per_cu;
+    }
+    if (t.kernel < 0 || t.kernel > 2) return fail(PIC_ERR_ARG, "bad kernel form");
+    if (t.block < 64 || t.block > 512 || t.block % 64) return fail(PIC_ERR_ARG, "block must be 64..512, multiple of 64");
+    if (t.chunk < 1) return fail(PIC_ERR_ARG, "chunk must be >= 1");
+    if (t.wg_per_cu < 1 || t.wg_per_cu > 64) return fail(PIC_ERR_ARG, "wg_per_cu must be 1..64");
+
+    pic_ctx *c = new pic_ctx();
+    c->nboxes = nboxes;
+    c->order = boxes[0].order;
+    c->prec = prec;
+    c->stream = (hipStream_t)stream;
+    c->tun = t;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&c->cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+        delete c;
+        return fail(PIC_ERR_DEVICE, "no HIP device");
+    }
+    const int o = c->order;
+    const size_t fb = prec == PIC_FP64 ? 8 : 4;
+    size_t fmax = 0, jmax = 0;
+    c->hfp.assign(nboxes + 1, 0);
+    for (int i = 0; i < nboxes; ++i) {
+        const pic_box_desc &b = boxes[i];
+        DevBox d;
+        std::memset(&d, 0, sizeof(d));
+        d.dim = b.dim;
+        d.order = b.order;
+        d.ncells = 1;
+        d.small = 0;
+        size_t fr = 6 * fb, jr = 3 * fb;
+        for (int k = 0; k < 3; ++k) {
+            d.n[k] = b.n[k];
+            d.tile[k] = b.tile[k];
+            d.nt[k] = (b.n[k] + b.tile[k] - 1) / b.tile[k];
+            d.dx[k] = b.dx[k];
+            d.ncells *= b.n[k];
+            const bool active = !(b.dim == 2 && k == 1);
+            if (active) {
+                int te = std::min(b.tile[k], b.n[k]);
+                fr *= (size_t)(te + halo_gl(o) + halo_gh(o));
+                jr *= (size_t)(te + halo_jl(o) + halo_jh(o));
+                if (b.n[k] < 8) d.small = 1;
+            }
+        }
+        d.ntiles = d.nt[0] * d.nt[1] * d.nt[2];
+        d.cell_base = b.cell_base;
+        d.dt = b.dt;
+        fmax = std::max(fmax, fr);
+        jmax = std::max(jmax, jr);
+        c->hbox.push_back(d);
+        c->hfp[i + 1] = c->hfp[i] + d.ncells;
+    }
+    c->total_cells = c->hfp[nboxes];
+    c->lds_field_bytes = (fmax + 15) / 16 * 16;
+    c->lds_bytes = c->lds_field_bytes + jmax;
+    if (t.kernel != PIC_KERNEL_DIRECT && c->lds_bytes > (size_t)LDS_BYTES_MAX) {
+        delete c;
+        return fail(PIC_ERR_ARG, "tile too large: LDS need " + std::to_string(c->lds_bytes) + " bytes");
+    }
+    if ((st = dalloc(&c->dbox, (size_t)nboxes)) != PIC_OK ||
+        (st = dalloc(&c->dfp, (size_t)nboxes + 1)) != PIC_OK ||
+        (st = dalloc(&c->derr, 4)) != PIC_OK || (st = dalloc(&c->nitems, 4)) != PIC_OK ||
+        (st = dalloc(&c->queue, 4)) != PIC_OK) {
+        pic_free(c);
+        return st;
+    }
+    if (hipMemcpy(c->dbox, c->hbox.data(), nboxes * sizeof(DevBox), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(c->dfp, c->hfp.data(), (nboxes + 1) * sizeof(long long), hipMemcpyHostToDevice) != hipSuccess) {
+        pic_free(c);
+        return fail(PIC_ERR_DEVICE, "upload of box tables failed");
+    }
+    int zero[4] = {0, 0, 0, 0};
+    if (hipMemcpy(c->derr, zero, sizeof(zero), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(c->nitems, zero, sizeof(zero), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(c->queue, zero, sizeof(zero), hipMemcpyHostToDevice) != hipSuccess) {
+        pic_free(c);
+        return fail(PIC_ERR_DEVICE, "init of device flags failed");
+    }
+    if (t.kernel != PIC_KERNEL_DIRECT) {
+        const int precb = prec == PIC_FP64 ? 0 : 1;
+        hipError_t e = o == 1 ? particles_lds_limit_o1(precb, (int)c->lds_bytes)
+                              : (o == 2 ? particles_lds_limit_o2(precb, (int)c->lds_bytes)
+                                        : particles_lds_limit_o3(precb, (int)c->lds_bytes));
+        if (e != hipSuccess) {
+            pic_free(c);
+            return fail(PIC_ERR_DEVICE, std::string("LDS limit: ") + hipGetErrorString(e));
+        }
+    }
+    *out = c;
+    return PIC_OK;
+}
+
+pic_status pic_sort_tiles(pic_ctx *c, const pic_species *sp, int32_t nsp, int32_t *const *perm_out,
+                          int32_t *const *key_out, int32_t *const *tile_offset_out) {
+    return do_sort(c, sp, nsp, perm_out, key_out, tile_offset_out);
+}
+
+pic_status pic_gather_push(pic_ctx *c, const pic_fields *f, pic_species *sp, int32_t nsp) {
+    return run_particles(c, const_cast<pic_fields *>(f), sp, nsp, MODE_PUSH);
+}
+
+pic_status pic_deposit_J(pic_ctx *c, pic_fields *f, pic_species *sp, int32_t nsp) {
+    return run_particles(c, f, sp, nsp, MODE_DEPOSIT);
+}
+
+pic_status pic_advance(pic_ctx *c, pic_fields *f, pic_species *sp, int32_t nsp) {
+    return run_particles(c, f, sp, nsp, MODE_FUSED);
+}
+
+pic_status pic_fdtd_step(pic_ctx *c, pic_fields *f) { return do_fdtd(c, f); }
+
+pic_status pic_step(pic_ctx *c, pic_fields *f, pic_species *sp, int32_t nsp, int32_t sort) {
+    if (!c) return fail(PIC_ERR_ARG, "ctx is NULL");
+    pic_status st = check_fields(c, f, true);
+    if (st != PIC_OK) return st;
+    if ((st = bind_species(c, sp, nsp, false)) != PIC_OK) return st;
+    if (c->tun.kernel != PIC_KERNEL_DIRECT && !sort) {
+        for (int s = 0; s < nsp; ++s)
+            if (!c->slots[s].sorted && sp[s].np > 0)
+                return fail(PIC_ERR_STATE, "tiled kernels need a sort before the first step");
+    }
+    // key: fields, species table, sort flag
+    std::string key((const char *)f, sizeof(pic_fields));
+    key.append((const char *)c->hsp.data(), c->hsp.size() * sizeof(DevSpecies));
+    key.push_back(sort ? 'S' : 'N');
+    auto it = c->graphs.find(key);
+    if (it == c->graphs.end()) {
+        // size every scratch buffer before capture starts
+        long long maxnp = 0, nitems_cap = c->nslots + 1;
+        for (int s = 0; s < nsp; ++s) {
+            maxnp = std::max(maxnp, (long long)sp[s].np);
+            nitems_cap += (sp[s].np + c->tun.chunk - 1) / c->tun.chunk;
+        }
+        if (sort && (st = ensure_sort_scratch(c, maxnp, nitems_cap)) != PIC_OK) return st;
+        HIP_TRY(hipStreamSynchronize(c->stream));
+        if (!c->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+        hipGraph_t g = nullptr;
+        hipStream_t user = c->stream;
+        HIP_TRY(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+        c->stream = c->cap_stream;
+        c->capturing = true;
+        pic_status s1 = PIC_OK;
+        if (sort) s1 = do_sort(c, sp, nsp, nullptr, nullptr, nullptr);
+        if (s1 == PIC_OK) s1 = run_particles(c, f, sp, nsp, MODE_FUSED);
+        if (s1 == PIC_OK) s1 = do_fdtd(c, f);
+        c->capturing = false;
+        c->stream = user;
+        hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+        if (s1 != PIC_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return s1;
+        }
+        if (e != hipSuccess) return fail(PIC_ERR_DEVICE, std::string("capture: ") + hipGetErrorString(e));
+        hipGraphExec_t ex = nullptr;
+        e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) return fail(PIC_ERR_DEVICE, std::string("instantiate: ") + hipGetErrorString(e));
+        it = c->graphs.emplace(key, ex).first;
+    } else {
+        // capture bookkeeping done at record time; mirror its effect
+        for (int s = 0; s < nsp; ++s) {
+            if (sort) c->slots[s].sorted = true;
+            c->slots[s].pushed = false;
+        }
+    }
+    HIP_TRY(hipGraphLaunch(it->second, c->stream));
+    return PIC_OK;
+}
+
+pic_status pic_deposit_rho(pic_ctx *c, const pic_species *sp, int32_t nsp, int32_t box, double *rho) {
+    if (!c) return fail(PIC_ERR_ARG, "ctx is NULL");
+    if (box < 0 || box >= c->nboxes || !rho) return fail(PIC_ERR_ARG, "bad box or rho");
+    pic_status st = bind_species(c, sp, nsp, false);
+    if (st != PIC_OK) return st;
+    KParams k = make_params(c, nullptr, nsp);
+    const int prec = c->prec == PIC_FP64 ? 0 : 1;
+    for (int s = 0; s < nsp; ++s) {
+        if (sp[s].box != box || sp[s].np == 0) continue;
+        hipError_t e = c->order == 1 ? launch_rho_o1(k, prec, s, sp[s].np, rho, c->stream)
+                                     : (c->order == 2 ? launch_rho_o2(k, prec, s, sp[s].np, rho, c->stream)
+                                                      : launch_rho_o3(k, prec, s, sp[s].np, rho, c->stream));
+        HIP_TRY(e);
+    }
+    return PIC_OK;
+}
+
+pic_status pic_div_edge(pic_ctx *c, int32_t box, double *const v[3], double *out) {
+    if (!c) return fail(PIC_ERR_ARG, "ctx is NULL");
+    if (box < 0 || box >= c->nboxes || !v || !out || !v[0] || !v[1] || !v[2])
+        return fail(PIC_ERR_ARG, "bad box or pointers");
+    HIP_TRY(launch_div_edge(c->dbox, box, c->hbox[box].ncells, v, out, c->stream));
+    return PIC_OK;
+}
+
+pic_status pic_check(pic_ctx *c) {
+    if (!c) return fail(PIC_ERR_ARG, "ctx is NULL");
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    int flag = 0;
+    HIP_TRY(hipMemcpy(&flag, c->derr, sizeof(int), hipMemcpyDeviceToHost));
+    if (flag) {
+        HIP_TRY(launch_set_int(c->derr, 0, c->stream));
+        HIP_TRY(hipStreamSynchronize(c->stream));
+        return fail(PIC_ERR_RANGE, "a particle moved >= 1 cell in a step, or a value was not finite");
+    }
+    return PIC_OK;
+}
+
+pic_status pic_free(pic_ctx *c) {
+    if (!c) return PIC_OK;
+    (void)hipStreamSynchronize(c->stream);
+    for (auto &kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    for (auto &sl : c->slots) {
+        for (int d = 0; d < 3; ++d) { dfree(sl.xo[d]); dfree(sl.offo[d]); }
+        dfree(sl.cello);
+        dfree(sl.carry);
+        dfree(sl.tile_off);
+    }
+    for (int i = 0; i < 2; ++i) { dfree(c->keys[i]); dfree(c->vals[i]); }
+    if (c->tmp) (void)hipFree(c->tmp);
+    dfree(c->counts);
+    dfree(c->scan_scr);
+    dfree(c->items);
+    dfree(c->item_counts);
+    dfree(c->item_starts);
+    dfree(c->nitems);
+    dfree(c->queue);
+    dfree(c->dsp);
+    dfree(c->dprefix);
+    dfree(c->dbox);
+    dfree(c->dfp);
+    dfree(c->derr);
+    delete c;
+    return PIC_OK;
+}
+
+int32_t pic_device_cus(pic_ctx *c) { return c ? c->cus : 0; }
+
+}  // extern "C"

@@ -1,0 +1,500 @@
+// Non-particle kernels of libpic: the per-tile stable counting sort (LSD
+// radix passes of 8 bits over the tile id, each pass a stable counting sort),
+// device-wide exclusive scan, per-tile offsets, permutation of the particle
+// arrays, work-item list of the batched kernel, J zeroing, the Yee FDTD
+// update over all boxes, and the node divergence used by the continuity
+// check.
+#include "pic_dev.h"
+#include "pic_math.h"
+#include "pic_aux.h"
+
+namespace pic {
+namespace {
+
+constexpr int SBS = 256;           // sort/scan block size (4 waves)
+constexpr int SIPT = 16;           // sort items per thread
+constexpr int SITEMS = SBS * SIPT; // elements per sort block
+constexpr int SCAN_IPT = 4;
+constexpr int SCAN_ITEMS = SBS * SCAN_IPT;
+
+__device__ inline int lane_id() { return threadIdx.x & 63; }
+__device__ inline int wave_id() { return threadIdx.x >> 6; }
+
+// ------------------------------------------------------------ keys
+
+template <int PREC>
+__global__ void k_tile_keys(const DevSpecies *spt, int s, const DevBox *boxes, int *key,
+                            int *val, int *err) {
+    const DevSpecies &sp = spt[s];
+    const DevBox &b = boxes[sp.box];
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= sp.np) return;
+    int c[3] = {0, 0, 0};
+    bool ok = true;
+    if (PREC == 0) {
+        #pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            if (b.dim == 2 && d == 1) continue;
+            double x = sp.x[d][i];
+            if (!(x >= 0.0 && x < (double)b.n[d])) { ok = false; break; }
+            c[d] = (int)floor(x);
+        }
+    } else {
+        int cell = sp.cell[i];
+        if (cell < 0 || (long long)cell >= b.ncells) ok = false;
+        else {
+            int nxy = b.n[0] * b.n[1];
+            c[2] = cell / nxy;
+            int r = cell - c[2] * nxy;
+            c[1] = r / b.n[0];
+            c[0] = r - c[1] * b.n[0];
+        }
+    }
+    int k;
+    if (ok) {
+        k = c[0] / b.tile[0] + b.nt[0] * (c[1] / b.tile[1] + b.nt[1] * (c[2] / b.tile[2]));
+    } else {
+        k = b.ntiles;       // bucket of invalid particles, after every tile
+        atomicOr(err, 1);
+    }
+    key[i] = k;
+    val[i] = (int)i;
+}
+
+// ------------------------------------------------------------ radix passes
+
+// Lanes of this wave whose 8-bit digit equals ours (among valid lanes).
+__device__ inline unsigned long long peers(int digit, bool valid) {
+    unsigned long long m = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+        int bit = (digit >> b) & 1;
+        unsigned long long bal = __ballot(bit);
+        m &= bit ? bal : ~bal;
+    }
+    return m;
+}
+
+__global__ void __launch_bounds__(SBS) k_radix_up(const int *key, long long n, int shift,
+                                                  int *counts, int nblocks) {
+    __shared__ int hist[256];
+    hist[threadIdx.x] = 0;
+    __syncthreads();
+    const long long base = (long long)blockIdx.x * SITEMS;
+    const unsigned long long below = (1ull << lane_id()) - 1ull;
+    for (int r = 0; r < SIPT; ++r) {
+        long long e = base + (long long)r * SBS + threadIdx.x;
+        bool valid = e < n;
+        int d = valid ? ((key[e] >> shift) & 255) : 0;
+        unsigned long long m = peers(d, valid);
+        if (valid && (m & below) == 0ull) atomicAdd(&hist[d], __popcll(m));
+    }
+    __syncthreads();
+    counts[(long long)threadIdx.x * nblocks + blockIdx.x] = hist[threadIdx.x];
+}
+
+__global__ void __launch_bounds__(SBS) k_radix_down(const int *key_in, const int *val_in,
+                                                    int *key_out, int *val_out, long long n,
+                                                    int shift, const int *offsets, int nblocks) {
+    __shared__ int run[256];
+    __shared__ int wcnt[SBS / 64][256];
+    run[threadIdx.x] = offsets[(long long)threadIdx.x * nblocks + blockIdx.x];
+    for (int w = 0; w < SBS / 64; ++w) wcnt[w][threadIdx.x] = 0;
+    __syncthreads();
+    const long long base = (long long)blockIdx.x * SITEMS;
+    const int lane = lane_id(), wave = wave_id();
+    const unsigned long long below = (1ull << lane) - 1ull;
+    for (int r = 0; r < SIPT; ++r) {
+        long long e = base + (long long)r * SBS + threadIdx.x;
+        bool valid = e < n;
+        int k = valid ? key_in[e] : 0;
+        int v = valid ? val_in[e] : 0;
+        int d = (k >> shift) & 255;
+        unsigned long long m = peers(d, valid);
+        int rank = __popcll(m & below);
+        if (valid && rank == 0) wcnt[wave][d] = __popcll(m);
+        __syncthreads();
+        if (valid) {
+            int pos = run[d] + rank;
+            for (int w = 0; w < wave; ++w) pos += wcnt[w][d];
+            key_out[pos] = k;
+            val_out[pos] = v;
+        }
+        __syncthreads();
+        int tot = 0;
+        for (int w = 0; w < SBS / 64; ++w) { tot += wcnt[w][threadIdx.x]; wcnt[w][threadIdx.x] = 0; }
+        run[threadIdx.x] += tot;
+        __syncthreads();
+    }
+}
+
+// offsets[t] = first sorted position whose key is >= t, t = 0 .. nkeys.
+__global__ void k_tile_offsets(const int *key, long long n, int nkeys, int *off) {
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > n) return;
+    int prev = (i == 0) ? -1 : key[i - 1];
+    int cur = (i == n) ? nkeys : key[i];
+    for (int t = prev + 1; t <= cur; ++t) off[t] = (int)i;
+}
+
+// ------------------------------------------------------------ scan
+
+__device__ inline int wave_incl_scan(int v) {
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        int t = __shfl_up(v, o, 64);
+        if (lane_id() >= o) v += t;
+    }
+    return v;
+}
+
+// Exclusive scan of SCAN_ITEMS consecutive elements per block; block total
+// to sums[blockIdx].
+__global__ void __launch_bounds__(SBS) k_scan_block(const int *in, int *out, long long n,
+                                                    int *sums) {
+    __shared__ int buf[SCAN_ITEMS];
+    __shared__ int wtot[SBS / 64];
+    const long long base = (long long)blockIdx.x * SCAN_ITEMS;
+    for (int r = 0; r < SCAN_IPT; ++r) {
+        long long e = base + r * SBS + threadIdx.x;
+        buf[r * SBS + threadIdx.x] = e < n ? in[e] : 0;
+    }
+    __syncthreads();
+    int loc[SCAN_IPT];
+    int t = 0;
+    for (int r = 0; r < SCAN_IPT; ++r) { loc[r] = t; t += buf[threadIdx.x * SCAN_IPT + r]; }
+    int inc = wave_incl_scan(t);
+    if (lane_id() == 63) wtot[wave_id()] = inc;
+    __syncthreads();
+    int wpre = 0;
+    for (int w = 0; w < wave_id(); ++w) wpre += wtot[w];
+    int excl = wpre + inc - t;
+    for (int r = 0; r < SCAN_IPT; ++r) buf[threadIdx.x * SCAN_IPT + r] = excl + loc[r];
+    if (threadIdx.x == SBS - 1) sums[blockIdx.x] = excl + t;
+    __syncthreads();
+    for (int r = 0; r < SCAN_IPT; ++r) {
+        long long e = base + r * SBS + threadIdx.x;
+        if (e < n) out[e] = buf[r * SBS + threadIdx.x];
+    }
+}
+
+__global__ void k_scan_add(int *out, long long n, const int *sums_scanned) {
+    long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < n) out[e] += sums_scanned[e / SCAN_ITEMS];
+}
+
+// total = last exclusive value + last input (n >= 1), or 0.
+__global__ void k_scan_total(const int *in, const int *out, long long n, int *total) {
+    *total = n > 0 ? out[n - 1] + in[n - 1] : 0;
+}
+
+// ------------------------------------------------------------ permutation
+
+template <typename T>
+__global__ void k_gather(const T *src, const int *perm, T *dst, long long n) {
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[perm[i]];
+}
+
+template <typename T>
+__global__ void k_copy(const T *src, T *dst, long long n) {
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[i];
+}
+
+// ------------------------------------------------------------ work items
+
+__device__ inline int slot_species(const int *prefix, int nsp, int g) {
+    int s = 0;
+    while (s + 1 < nsp && prefix[s + 1] <= g) ++s;
+    return s;
+}
+
+__global__ void k_item_count(const DevSpecies *spt, const int *prefix, int nsp, int nslots,
+                             int chunk, int *counts) {
+    int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= nslots) return;
+    int s = slot_species(prefix, nsp, g);
+    int t = g - prefix[s];
+    const int *off = spt[s].tile_off;
+    int n = off[t + 1] - off[t];
+    counts[g] = (n + chunk - 1) / chunk;
+}
+
+__global__ void k_item_fill(const DevSpecies *spt, const int *prefix, int nsp, int nslots,
+                            int chunk, const int *starts, Item *items) {
+    int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= nslots) return;
+    int s = slot_species(prefix, nsp, g);
+    int t = g - prefix[s];
+    const int *off = spt[s].tile_off;
+    int p0 = off[t], p1 = off[t + 1];
+    int st = starts[g];
+    for (int c = 0; p0 + c * chunk < p1; ++c) {
+        int a = p0 + c * chunk;
+        items[st + c] = Item{s, t, a, min(p1, a + chunk)};
+    }
+}
+
+__global__ void k_set_int(int *p, int v) { *p = v; }
+
+// ------------------------------------------------------------ fields
+
+__device__ inline int box_of(const long long *fp, int nb, long long g) {
+    int lo = 0, hi = nb - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (fp[mid] <= g) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ void k_zero_j(DevFields f, const DevBox *boxes, const long long *fp, int nb,
+                         long long total) {
+    long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= total) return;
+    int b = box_of(fp, nb, g);
+    long long c = boxes[b].cell_base + (g - fp[b]);
+    f.J[0][c] = 0.0;
+    f.J[1][c] = 0.0;
+    f.J[2][c] = 0.0;
+}
+
+struct CellNbr {
+    long long c, xp, yp, zp, xm, ym, zm;
+};
+
+__device__ inline CellNbr neighbours(const DevBox &b, long long local) {
+    const int n0 = b.n[0], n1 = b.n[1], n2 = b.n[2];
+    int i = (int)(local % n0);
+    long long r = local / n0;
+    int j = (int)(r % n1);
+    int k = (int)(r / n1);
+    int ip = (i + 1 == n0) ? 0 : i + 1, im = (i == 0) ? n0 - 1 : i - 1;
+    int jp = (j + 1 == n1) ? 0 : j + 1, jm = (j == 0) ? n1 - 1 : j - 1;
+    int kp = (k + 1 == n2) ? 0 : k + 1, km = (k == 0) ? n2 - 1 : k - 1;
+    auto id = [&](int a, int bb, int cc) {
+        return b.cell_base + a + (long long)n0 * (bb + (long long)n1 * cc);
+    };
+    return CellNbr{id(i, j, k), id(ip, j, k), id(i, jp, k), id(i, j, kp),
+                   id(im, j, k), id(i, jm, k), id(i, j, km)};
+}
+
+// B -= h curl E, curl E at the B points (Yee).  2D: no d/dy terms.
+template <typename T>
+__global__ void k_faraday(DevFields f, const DevBox *boxes, const long long *fp, int nb,
+                          long long total, double hfrac) {
+    long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= total) return;
+    int bi = box_of(fp, nb, g);
+    const DevBox &b = boxes[bi];
+    CellNbr q = neighbours(b, g - fp[bi]);
+    const T *Ex = (const T *)f.E[0], *Ey = (const T *)f.E[1], *Ez = (const T *)f.E[2];
+    T *Bx = (T *)f.B[0], *By = (T *)f.B[1], *Bz = (T *)f.B[2];
+    const T h = (T)(hfrac * b.dt);
+    const T ix = (T)(1.0 / b.dx[0]), iy = (T)(1.0 / b.dx[1]), iz = (T)(1.0 / b.dx[2]);
+    T ez = Ez[q.c], ey = Ey[q.c], ex = Ex[q.c];
+    T dEz_dy = T(0), dEx_dy = T(0);
+    if (b.dim == 3) { dEz_dy = (Ez[q.yp] - ez) * iy; dEx_dy = (Ex[q.yp] - ex) * iy; }
+    T cx = dEz_dy - (Ey[q.zp] - ey) * iz;
+    T cy = (Ex[q.zp] - ex) * iz - (Ez[q.xp] - ez) * ix;
+    T cz = (Ey[q.xp] - ey) * ix - dEx_dy;
+    Bx[q.c] -= h * cx;
+    By[q.c] -= h * cy;
+    Bz[q.c] -= h * cz;
+}
+
+// E += dt (curl B - J), curl B at the E points.
+template <typename T>
+__global__ void k_ampere(DevFields f, const DevBox *boxes, const long long *fp, int nb,
+                         long long total) {
+    long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= total) return;
+    int bi = box_of(fp, nb, g);
+    const DevBox &b = boxes[bi];
+    CellNbr q = neighbours(b, g - fp[bi]);
+    T *Ex = (T *)f.E[0], *Ey = (T *)f.E[1], *Ez = (T *)f.E[2];
+    const T *Bx = (const T *)f.B[0], *By = (const T *)f.B[1], *Bz = (const T *)f.B[2];
+    const T dt = (T)b.dt;
+    const T ix = (T)(1.0 / b.dx[0]), iy = (T)(1.0 / b.dx[1]), iz = (T)(1.0 / b.dx[2]);
+    T bx = Bx[q.c], by = By[q.c], bz = Bz[q.c];
+    T dBz_dy = T(0), dBx_dy = T(0);
+    if (b.dim == 3) { dBz_dy = (bz - Bz[q.ym]) * iy; dBx_dy = (bx - Bx[q.ym]) * iy; }
+    T cx = dBz_dy - (by - By[q.zm]) * iz;
+    T cy = (bx - Bx[q.zm]) * iz - (bz - Bz[q.xm]) * ix;
+    T cz = (by - By[q.xm]) * ix - dBx_dy;
+    Ex[q.c] += dt * (cx - (T)f.J[0][q.c]);
+    Ey[q.c] += dt * (cy - (T)f.J[1][q.c]);
+    Ez[q.c] += dt * (cz - (T)f.J[2][q.c]);
+}
+
+// Node divergence of an E-staggered vector field (FP64).
+__global__ void k_div_edge(const DevBox *boxes, int bi, const double *vx, const double *vy,
+                           const double *vz, double *out) {
+    const DevBox &b = boxes[bi];
+    long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= b.ncells) return;
+    CellNbr q = neighbours(b, g);
+    long long base = b.cell_base;
+    double d = (vx[q.c] - vx[q.xm]) / b.dx[0] + (vz[q.c] - vz[q.zm]) / b.dx[2];
+    if (b.dim == 3) d += (vy[q.c] - vy[q.ym]) / b.dx[1];
+    out[q.c - base] = d;
+}
+
+inline unsigned blocks_for(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+}  // namespace
+
+// ============================================================ host launchers
+
+hipError_t launch_tile_keys(int prec, const DevSpecies *spt, int s, long long np,
+                            const DevBox *boxes, int *key, int *val, int *err, hipStream_t st) {
+    if (np == 0) return hipSuccess;
+    if (prec == 0)
+        hipLaunchKernelGGL(k_tile_keys<0>, dim3(blocks_for(np, 256)), dim3(256), 0, st, spt, s,
+                           boxes, key, val, err);
+    else
+        hipLaunchKernelGGL(k_tile_keys<1>, dim3(blocks_for(np, 256)), dim3(256), 0, st, spt, s,
+                           boxes, key, val, err);
+    return hipGetLastError();
+}
+
+size_t scan_scratch_ints(long long n) {
+    size_t tot = 0;
+    while (n > 1) {
+        long long nb = (n + SCAN_ITEMS - 1) / SCAN_ITEMS;
+        tot += (size_t)nb + 64;
+        n = nb;
+    }
+    return tot + 64;
+}
+
+// Exclusive scan of in[0..n) into out (may alias in? no: distinct buffers
+// not required, the block pass reads before it writes its own range).
+hipError_t scan_exclusive(const int *in, int *out, long long n, int *total, int *scratch,
+                          hipStream_t st) {
+    if (n <= 0) {
+        if (total) hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, st, total, 0);
+        return hipGetLastError();
+    }
+    long long nb = (n + SCAN_ITEMS - 1) / SCAN_ITEMS;
+    int *sums = scratch;
+    int *rest = scratch + nb + 64;
+    if (total) {
+        // the total needs the unscanned last input; read it before out may alias in
+        hipLaunchKernelGGL(k_copy<int>, dim3(1), dim3(1), 0, st, in + (n - 1), total, 1ll);
+    }
+    hipLaunchKernelGGL(k_scan_block, dim3((unsigned)nb), dim3(SBS), 0, st, in, out, n, sums);
+    if (nb > 1) {
+        hipError_t e = scan_exclusive(sums, sums, nb, nullptr, rest, st);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_scan_add, dim3(blocks_for(n, 256)), dim3(256), 0, st, out, n,
+                           (const int *)sums);
+    }
+    if (total) {
+        // total = last input (already in *total) + last exclusive output
+        hipLaunchKernelGGL(k_scan_total, dim3(1), dim3(1), 0, st, (const int *)total,
+                           (const int *)(out + (n - 1)), 1ll, total);
+    }
+    return hipGetLastError();
+}
+
+int radix_blocks(long long n) { return (int)((n + SITEMS - 1) / SITEMS); }
+
+hipError_t radix_pass(const int *kin, const int *vin, int *kout, int *vout, long long n,
+                      int shift, int *counts, int *scan_scratch, hipStream_t st) {
+    int nb = radix_blocks(n);
+    if (nb == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_radix_up, dim3(nb), dim3(SBS), 0, st, kin, n, shift, counts, nb);
+    hipError_t e = scan_exclusive(counts, counts, (long long)nb * 256, nullptr, scan_scratch, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_radix_down, dim3(nb), dim3(SBS), 0, st, kin, vin, kout, vout, n, shift,
+                       (const int *)counts, nb);
+    return hipGetLastError();
+}
+
+hipError_t launch_tile_offsets(const int *key, long long n, int nkeys, int *off, hipStream_t st) {
+    hipLaunchKernelGGL(k_tile_offsets, dim3(blocks_for(n + 1, 256)), dim3(256), 0, st, key, n,
+                       nkeys, off);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather4(const void *src, const int *perm, void *dst, long long n, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gather<int>, dim3(blocks_for(n, 256)), dim3(256), 0, st,
+                       (const int *)src, perm, (int *)dst, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather8(const void *src, const int *perm, void *dst, long long n, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gather<long long>, dim3(blocks_for(n, 256)), dim3(256), 0, st,
+                       (const long long *)src, perm, (long long *)dst, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy4(const void *src, void *dst, long long n, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_copy<int>, dim3(blocks_for(n, 256)), dim3(256), 0, st, (const int *)src,
+                       (int *)dst, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy8(const void *src, void *dst, long long n, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_copy<long long>, dim3(blocks_for(n, 256)), dim3(256), 0, st,
+                       (const long long *)src, (long long *)dst, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_items(const DevSpecies *spt, const int *prefix, int nsp, int nslots, int chunk,
+                        int *counts, int *starts, int *scan_scratch, Item *items, int *nitems,
+                        int *queue, hipStream_t st) {
+    hipLaunchKernelGGL(k_item_count, dim3(blocks_for(nslots, 256)), dim3(256), 0, st, spt, prefix,
+                       nsp, nslots, chunk, counts);
+    hipError_t e = scan_exclusive(counts, starts, nslots, nitems, scan_scratch, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_item_fill, dim3(blocks_for(nslots, 256)), dim3(256), 0, st, spt, prefix,
+                       nsp, nslots, chunk, (const int *)starts, items);
+    hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, st, queue, 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_int(int *p, int v, hipStream_t st) {
+    hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, st, p, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_j(const DevFields &f, const DevBox *boxes, const long long *fp, int nb,
+                         long long total, hipStream_t st) {
+    if (total == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero_j, dim3(blocks_for(total, 256)), dim3(256), 0, st, f, boxes, fp, nb,
+                       total);
+    return hipGetLastError();
+}
+
+hipError_t launch_fdtd(int prec, const DevFields &f, const DevBox *boxes, const long long *fp,
+                       int nb, long long total, hipStream_t st) {
+    if (total == 0) return hipSuccess;
+    dim3 g(blocks_for(total, 256)), b(256);
+    if (prec == 0) {
+        hipLaunchKernelGGL(k_faraday<double>, g, b, 0, st, f, boxes, fp, nb, total, 0.5);
+        hipLaunchKernelGGL(k_ampere<double>, g, b, 0, st, f, boxes, fp, nb, total);
+        hipLaunchKernelGGL(k_faraday<double>, g, b, 0, st, f, boxes, fp, nb, total, 0.5);
+    } else {
+        hipLaunchKernelGGL(k_faraday<float>, g, b, 0, st, f, boxes, fp, nb, total, 0.5);
+        hipLaunchKernelGGL(k_ampere<float>, g, b, 0, st, f, boxes, fp, nb, total);
+        hipLaunchKernelGGL(k_faraday<float>, g, b, 0, st, f, boxes, fp, nb, total, 0.5);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_div_edge(const DevBox *boxes, int bi, long long ncells, double *const v[3],
+                           double *out, hipStream_t st) {
+    if (ncells == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_div_edge, dim3(blocks_for(ncells, 256)), dim3(256), 0, st, boxes, bi,
+                       (const double *)v[0], (const double *)v[1], (const double *)v[2], out);
+    return hipGetLastError();
+}
+
+}  // namespace pic

@@ -1,0 +1,74 @@
+// Device-side descriptors of libpic (boxes, species, fields, launch
+// parameters) and the declarations of the kernel launchers.  Internal to the
+// library; the public interface is include/libpic.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pic {
+
+struct DevBox {
+    int dim;            // 2 or 3
+    int order;
+    int n[3];
+    int tile[3];
+    int nt[3];          // tiles per axis
+    int ntiles;
+    int small;          // 1 if some n[d] is below the widest stencil (needs
+                        // general modulo wrapping)
+    long long cell_base;
+    long long ncells;
+    double dt;
+    double dx[3];
+};
+
+struct DevSpecies {
+    long long np;
+    double q, m;
+    int box;
+    int tile_base;      // first (species, tile) slot of this species
+    double *x[3];
+    int *cell;
+    float *off[3];
+    void *u[3];
+    void *w;
+    // scratch of the split push/deposit: x^n
+    double *xo[3];
+    int *cello;
+    float *offo[3];
+    int *carry;         // split: cell change per axis, 2 bits each (+1)
+    // exclusive per-tile offsets from the last sort, ntiles+2 entries
+    // (the extra bucket holds particles with invalid positions)
+    int *tile_off;
+};
+
+struct DevFields {
+    void *E[3];
+    void *B[3];
+    double *J[3];
+};
+
+// Work item of the batched kernel: species, tile, first and last particle.
+struct Item {
+    int s, t, p0, p1;
+};
+
+enum Mode { MODE_PUSH = 1, MODE_DEPOSIT = 2, MODE_FUSED = 3 };
+
+struct KParams {
+    const DevBox *boxes;
+    const DevSpecies *species;
+    int nsp;
+    DevFields f;
+    int *err;                 // device error flag (bit 0: range)
+    // TILED: block b -> species via prefix of tiles (nsp+1 entries)
+    const int *sp_tile_prefix;
+    // BATCHED: persistent queue of items
+    const Item *items;
+    const int *nitems;
+    int *queue;
+    int lds_field_bytes;      // offset of the J region in dynamic LDS
+};
+
+}  // namespace pic

@@ -1,0 +1,735 @@
+// Particle kernels of libpic: field gather, Boris push, position advance and
+// Esirkepov current deposit, for one B-spline order (PIC_ORDER, set by the
+// build: this file is compiled once per order).
+//
+// Three launch forms share one per-particle routine:
+//   direct   one thread per particle; E/B read from global memory, J added
+//            with global FP64 atomics.  Needs no sort.
+//   tiled    one workgroup per (species, tile): the tile's E/B plus halo is
+//            staged in LDS, J is accumulated in an LDS tile plus halo and
+//            flushed once with global FP64 atomics.
+//   batched  the tiled body driven by a persistent grid that pops
+//            (species, tile, particle chunk) items from a global queue, so
+//            tiles of very uneven population and many boxes share a launch.
+// A particle whose cell has left its tile since the last sort takes the
+// global-memory path inside the tiled forms, so results never depend on how
+// stale the sort is.
+//
+// Precision policies: F64 (FP64 positions, momenta, fields, LDS J) and
+// Split (int32 cell + FP32 in-cell offset, FP32 momenta, fields, gather,
+// push, LDS J; J flushed to FP64).
+#include "pic_dev.h"
+#include "pic_math.h"
+#include "pic_aux.h"
+
+#ifndef PIC_ORDER
+#error "PIC_ORDER must be defined (1, 2 or 3)"
+#endif
+
+namespace pic {
+namespace {
+
+constexpr int O = PIC_ORDER;
+using H = Halo<O>;
+
+__device__ inline void flag_range(int *err) { atomicOr(err, 1); }
+
+// ------------------------------------------------------------ precision
+
+struct F64 {
+    using R = double;
+    using FieldT = double;
+    using Acc = double;
+    static constexpr int PREC = 0;
+    // Old position from the species arrays or from scratch.
+    __device__ static bool load(const DevBox &b, double *const xs[3], long long i,
+                                int c[3], double f[3]) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            if (b.dim == 2 && d == 1) { c[d] = 0; f[d] = 0.0; continue; }
+            double x = xs[d][i];
+            if (!(x >= 0.0 && x < (double)b.n[d])) return false;
+            double fl = floor(x);
+            c[d] = (int)fl;
+            f[d] = x - fl;
+        }
+        return true;
+    }
+};
+
+struct Split {
+    using R = float;
+    using FieldT = float;
+    using Acc = float;
+    static constexpr int PREC = 1;
+    __device__ static bool load(const DevBox &b, const int *cells, float *const offs[3],
+                                long long i, int c[3], float f[3]) {
+        int cell = cells[i];
+        if (cell < 0 || (long long)cell >= b.ncells) return false;
+        int nx = b.n[0], nxy = b.n[0] * b.n[1];
+        c[2] = cell / nxy;
+        int r = cell - c[2] * nxy;
+        c[1] = r / nx;
+        c[0] = r - c[1] * nx;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            if (b.dim == 2 && d == 1) { f[d] = 0.0f; continue; }
+            float v = offs[d][i];
+            if (!(v >= 0.0f && v < 1.0f)) return false;
+            f[d] = v;
+        }
+        return true;
+    }
+};
+
+// ------------------------------------------------------------ accessors
+
+template <typename T> struct GlobalField {
+    const T *F[6];
+    int n0, n1, n2;
+    bool any;
+    __device__ inline T load(int comp, int i, int j, int k) const {
+        if (any) {
+            i = wrap_index_any(i, n0); j = wrap_index_any(j, n1); k = wrap_index_any(k, n2);
+        } else {
+            i = wrap_index(i, n0); j = wrap_index(j, n1); k = wrap_index(k, n2);
+        }
+        return F[comp][i + (long long)n0 * (j + (long long)n1 * k)];
+    }
+};
+
+template <typename T> struct LdsField {
+    const T *base;
+    int o0, o1, o2, L0, L1, L012;
+    __device__ inline T load(int comp, int i, int j, int k) const {
+        return base[comp * L012 + (i - o0) + L0 * ((j - o1) + L1 * (k - o2))];
+    }
+};
+
+struct GlobalJ {
+    double *J[3];
+    int n0, n1, n2;
+    bool any;
+    template <typename V>
+    __device__ inline void add(int comp, int i, int j, int k, V v) const {
+        if (any) {
+            i = wrap_index_any(i, n0); j = wrap_index_any(j, n1); k = wrap_index_any(k, n2);
+        } else {
+            i = wrap_index(i, n0); j = wrap_index(j, n1); k = wrap_index(k, n2);
+        }
+        unsafeAtomicAdd(&J[comp][i + (long long)n0 * (j + (long long)n1 * k)], (double)v);
+    }
+};
+
+template <typename A> struct LdsJ {
+    A *base;
+    int o0, o1, o2, M0, M1, M012;
+    template <typename V>
+    __device__ inline void add(int comp, int i, int j, int k, V v) const {
+        unsafeAtomicAdd(&base[comp * M012 + (i - o0) + M0 * ((j - o1) + M1 * (k - o2))], (A)v);
+    }
+};
+
+// ------------------------------------------------------------ gather
+
+template <int DIM, typename R, class FA>
+__device__ inline R interp(const FA &fa, int comp, const GWin<O, R> &wx,
+                           const GWin<O, R> &wy, const GWin<O, R> &wz) {
+    R sum = R(0);
+    if (DIM == 3) {
+#pragma unroll
+        for (int kk = 0; kk <= O; ++kk) {
+            R sy = R(0);
+#pragma unroll
+            for (int jj = 0; jj <= O; ++jj) {
+                R sx = R(0);
+#pragma unroll
+                for (int ii = 0; ii <= O; ++ii)
+                    sx += wx.w[ii] * (R)fa.load(comp, wx.base + ii, wy.base + jj, wz.base + kk);
+                sy += wy.w[jj] * sx;
+            }
+            sum += wz.w[kk] * sy;
+        }
+    } else {
+#pragma unroll
+        for (int kk = 0; kk <= O; ++kk) {
+            R sx = R(0);
+#pragma unroll
+            for (int ii = 0; ii <= O; ++ii)
+                sx += wx.w[ii] * (R)fa.load(comp, wx.base + ii, 0, wz.base + kk);
+            sum += wz.w[kk] * sx;
+        }
+    }
+    return sum;
+}
+
+// Each component from its own Yee points: E_c is half-shifted along c,
+// B_c along the two other axes.
+template <int DIM, typename R, class FA>
+__device__ inline void gather(const FA &fa, const int c[3], const R f[3], R E[3], R B[3]) {
+    GWin<O, R> g0[3], g1[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        if (DIM == 2 && d == 1) {
+            g0[d].base = 0; g1[d].base = 0;
+#pragma unroll
+            for (int m = 0; m <= O; ++m) { g0[d].w[m] = R(0); g1[d].w[m] = R(0); }
+            continue;
+        }
+        g0[d] = gather_window<O, R>(c[d], f[d], 0);
+        g1[d] = gather_window<O, R>(c[d], f[d], 1);
+    }
+    E[0] = interp<DIM>(fa, 0, g1[0], g0[1], g0[2]);
+    E[1] = interp<DIM>(fa, 1, g0[0], g1[1], g0[2]);
+    E[2] = interp<DIM>(fa, 2, g0[0], g0[1], g1[2]);
+    B[0] = interp<DIM>(fa, 3, g0[0], g1[1], g1[2]);
+    B[1] = interp<DIM>(fa, 4, g1[0], g0[1], g1[2]);
+    B[2] = interp<DIM>(fa, 5, g1[0], g1[1], g0[2]);
+}
+
+// ------------------------------------------------------------ deposit
+
+// Esirkepov weights: W^x = dSx (S0y S0z + dSy S0z/2 + S0y dSz/2 + dSy dSz/3)
+// and cyclically; J along an axis is the running sum of its W over the
+// window, scaled by -q w / (dt * face area).  The last edge of each line
+// carries the sum of all dS (zero) and is not written.
+template <int DIM, typename R, class JA>
+__device__ inline void deposit(const JA &ja, const int c0[3], const R f0[3],
+                               const int c1[3], const R f1[3], R cq[3], R vy) {
+    constexpr int K = O + 2;
+    DWin<O, R> wx = deposit_window<O, R>(c0[0], f0[0], c1[0], f1[0]);
+    DWin<O, R> wz = deposit_window<O, R>(c0[2], f0[2], c1[2], f1[2]);
+    const R third = R(1.0 / 3.0);
+    if (DIM == 3) {
+        DWin<O, R> wy = deposit_window<O, R>(c0[1], f0[1], c1[1], f1[1]);
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+#pragma unroll
+            for (int j = 0; j < K; ++j) {
+                R t = wy.S0[j] * wz.S0[k] + R(0.5) * (wy.dS[j] * wz.S0[k] + wy.S0[j] * wz.dS[k]) +
+                      third * wy.dS[j] * wz.dS[k];
+                if (t == R(0)) continue;
+                R acc = R(0);
+#pragma unroll
+                for (int i = 0; i < K - 1; ++i) {
+                    acc += wx.dS[i] * t;
+                    ja.add(0, wx.base + i, wy.base + j, wz.base + k, cq[0] * acc);
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+#pragma unroll
+            for (int i = 0; i < K; ++i) {
+                R t = wz.S0[k] * wx.S0[i] + R(0.5) * (wz.dS[k] * wx.S0[i] + wz.S0[k] * wx.dS[i]) +
+                      third * wz.dS[k] * wx.dS[i];
+                if (t == R(0)) continue;
+                R acc = R(0);
+#pragma unroll
+                for (int j = 0; j < K - 1; ++j) {
+                    acc += wy.dS[j] * t;
+                    ja.add(1, wx.base + i, wy.base + j, wz.base + k, cq[1] * acc);
+                }
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+#pragma unroll
+            for (int i = 0; i < K; ++i) {
+                R t = wx.S0[i] * wy.S0[j] + R(0.5) * (wx.dS[i] * wy.S0[j] + wx.S0[i] * wy.dS[j]) +
+                      third * wx.dS[i] * wy.dS[j];
+                if (t == R(0)) continue;
+                R acc = R(0);
+#pragma unroll
+                for (int k = 0; k < K - 1; ++k) {
+                    acc += wz.dS[k] * t;
+                    ja.add(2, wx.base + i, wy.base + j, wz.base + k, cq[2] * acc);
+                }
+            }
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            R t = wz.S0[k] + R(0.5) * wz.dS[k];
+            if (t == R(0)) continue;
+            R acc = R(0);
+#pragma unroll
+            for (int i = 0; i < K - 1; ++i) {
+                acc += wx.dS[i] * t;
+                ja.add(0, wx.base + i, 0, wz.base + k, cq[0] * acc);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < K; ++i) {
+            R t = wx.S0[i] + R(0.5) * wx.dS[i];
+            if (t == R(0)) continue;
+            R acc = R(0);
+#pragma unroll
+            for (int k = 0; k < K - 1; ++k) {
+                acc += wz.dS[k] * t;
+                ja.add(2, wx.base + i, 0, wz.base + k, cq[2] * acc);
+            }
+        }
+        const R cy = cq[1] * vy;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+#pragma unroll
+            for (int i = 0; i < K; ++i) {
+                R a = wx.S0[i] * wz.S0[k] + R(0.5) * (wx.dS[i] * wz.S0[k] + wx.S0[i] * wz.dS[k]) +
+                      third * wx.dS[i] * wz.dS[k];
+                if (a != R(0)) ja.add(1, wx.base + i, 0, wz.base + k, cy * a);
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------ one particle
+
+struct Tile {
+    int t0[3], te[3];
+    __device__ inline bool holds(const int c[3]) const {
+        return c[0] >= t0[0] && c[0] < t0[0] + te[0] && c[1] >= t0[1] &&
+               c[1] < t0[1] + te[1] && c[2] >= t0[2] && c[2] < t0[2] + te[2];
+    }
+};
+
+template <int DIM, class P, int MODE, class FL, class JL>
+__device__ inline void particle(const DevBox &b, const DevSpecies &sp, long long i,
+                                const DevFields &gf, const Tile *tile, const FL *lf,
+                                const JL *lj, int *err) {
+    using R = typename P::R;
+    using FT = typename P::FieldT;
+    int c0[3], c1[3];
+    R f0[3], f1[3], u[3];
+    bool ok;
+    const bool any = b.small != 0;
+    if (MODE & MODE_PUSH) {
+        if constexpr (P::PREC == 0) ok = P::load(b, sp.x, i, c0, f0);
+        else ok = P::load(b, sp.cell, sp.off, i, c0, f0);
+    } else {
+        if constexpr (P::PREC == 0) ok = P::load(b, sp.xo, i, c0, f0);
+        else ok = P::load(b, sp.cello, sp.offo, i, c0, f0);
+    }
+    if (!ok) { flag_range(err); return; }
+    const bool local = tile != nullptr && tile->holds(c0);
+    const R *ua[3] = {(const R *)sp.u[0], (const R *)sp.u[1], (const R *)sp.u[2]};
+    u[0] = ua[0][i]; u[1] = ua[1][i]; u[2] = ua[2][i];
+    const R dt = (R)b.dt;
+    if (MODE & MODE_PUSH) {
+        R E[3], B[3];
+        if (local) {
+            gather<DIM, R>(*lf, c0, f0, E, B);
+        } else {
+            GlobalField<FT> g;
+#pragma unroll
+            for (int cc = 0; cc < 3; ++cc) {
+                g.F[cc] = (const FT *)gf.E[cc] + b.cell_base;
+                g.F[cc + 3] = (const FT *)gf.B[cc] + b.cell_base;
+            }
+            g.n0 = b.n[0]; g.n1 = b.n[1]; g.n2 = b.n[2]; g.any = any;
+            gather<DIM, R>(g, c0, f0, E, B);
+        }
+        const R h = (R)(sp.q * b.dt / (2.0 * sp.m));
+        boris<R>(h, E, B, u);
+        const R gi = R(1) / sqrt(R(1) + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+        R disp[3];
+        bool good = true;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            disp[d] = (DIM == 2 && d == 1) ? R(0) : dt * u[d] * gi / (R)b.dx[d];
+            // below one cell with margin for rounding, so the deposit window
+            // always spans at most O+2 nodes per axis
+            good = good && (fabs(disp[d]) < R(0.999));
+        }
+        if (!good) {
+            // Flag and leave the particle where it is; a later deposit of
+            // this push sees no motion (and so adds no current).
+            flag_range(err);
+            if (MODE == MODE_PUSH) {
+                if constexpr (P::PREC == 0) {
+#pragma unroll
+                    for (int d = 0; d < 3; ++d)
+                        if (!(DIM == 2 && d == 1)) sp.xo[d][i] = (double)c0[d] + f0[d];
+                } else {
+                    sp.cello[i] = sp.cell[i];
+#pragma unroll
+                    for (int d = 0; d < 3; ++d)
+                        if (!(DIM == 2 && d == 1)) sp.offo[d][i] = f0[d];
+                    sp.carry[i] = 0x15;      // (0 + 1) per axis: no cell change
+                }
+            }
+            return;
+        }
+        // new position (cell + offset, unwrapped cell index)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            if (DIM == 2 && d == 1) { c1[d] = 0; f1[d] = R(0); continue; }
+            if constexpr (P::PREC == 0) {
+                double x1 = ((double)c0[d] + f0[d]) + disp[d];
+                double fl = floor(x1);
+                c1[d] = (int)fl;
+                f1[d] = x1 - fl;
+            } else {
+                float fr = f0[d] + disp[d];
+                if (fr >= 1.0f) { c1[d] = c0[d] + 1; f1[d] = fr - 1.0f; }
+                else if (fr < 0.0f) {
+                    c1[d] = c0[d] - 1; f1[d] = fr + 1.0f;
+                    if (f1[d] == 1.0f) { f1[d] = 0.0f; c1[d] = c0[d]; }
+                } else { c1[d] = c0[d]; f1[d] = fr; }
+            }
+        }
+        if (MODE == MODE_PUSH) {
+            // keep x^n for the deposit; store x^(n+1) and u^(n+1/2)
+            R *uo[3] = {(R *)sp.u[0], (R *)sp.u[1], (R *)sp.u[2]};
+#pragma unroll
+            for (int d = 0; d < 3; ++d) uo[d][i] = u[d];
+            if constexpr (P::PREC == 0) {
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    if (DIM == 2 && d == 1) continue;
+                    sp.xo[d][i] = (double)c0[d] + f0[d];
+                    sp.x[d][i] = (double)c1[d] + f1[d];           // unwrapped
+                }
+            } else {
+                sp.cello[i] = sp.cell[i];
+                int carry = 0;
+                int cw[3];
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    cw[d] = c1[d];
+                    if (DIM == 2 && d == 1) continue;
+                    sp.offo[d][i] = f0[d];
+                    sp.off[d][i] = f1[d];
+                    carry |= (c1[d] - c0[d] + 1) << (2 * d);
+                    cw[d] = wrap_index(c1[d], b.n[d]);
+                }
+                sp.carry[i] = carry;
+                sp.cell[i] = cw[0] + b.n[0] * (cw[1] + b.n[1] * cw[2]);
+            }
+            return;
+        }
+    } else {
+        // DEPOSIT only: x^(n+1) from the species arrays
+        if constexpr (P::PREC == 0) {
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                if (DIM == 2 && d == 1) { c1[d] = 0; f1[d] = 0.0; continue; }
+                double x1 = sp.x[d][i];
+                double fl = floor(x1);
+                c1[d] = (int)fl;
+                f1[d] = x1 - fl;
+                if (c1[d] - c0[d] > 1 || c0[d] - c1[d] > 1 || !(x1 == x1)) { flag_range(err); return; }
+            }
+        } else {
+            const int carry = sp.carry[i];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                if (DIM == 2 && d == 1) { c1[d] = 0; f1[d] = 0.0f; continue; }
+                const int sd = ((carry >> (2 * d)) & 3) - 1;
+                if (sd > 1) { flag_range(err); return; }
+                c1[d] = c0[d] + sd;
+                f1[d] = sp.off[d][i];
+                if (!(f1[d] >= 0.0f && f1[d] < 1.0f)) { flag_range(err); return; }
+            }
+        }
+    }
+    // ---- deposit x^n -> x^(n+1)
+    {
+        const R wgt = ((const R *)sp.w)[i];
+        const double dV = b.dx[0] * b.dx[1] * b.dx[2];
+        R cq[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) cq[d] = (R)(-sp.q * b.dx[d] / (b.dt * dV)) * wgt;
+        R vy = R(0);
+        if (DIM == 2) {
+            // out-of-plane current q w v_y / dV
+            const R gi = R(1) / sqrt(R(1) + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+            cq[1] = (R)(sp.q / dV) * wgt;
+            vy = u[1] * gi;
+        }
+        bool jlocal = local;
+        if (MODE == MODE_DEPOSIT && tile != nullptr) jlocal = tile->holds(c0);
+        if (jlocal) {
+            deposit<DIM, R>(*lj, c0, f0, c1, f1, cq, vy);
+        } else {
+            GlobalJ g;
+#pragma unroll
+            for (int cc = 0; cc < 3; ++cc) g.J[cc] = gf.J[cc] + b.cell_base;
+            g.n0 = b.n[0]; g.n1 = b.n[1]; g.n2 = b.n[2]; g.any = any;
+            deposit<DIM, R>(g, c0, f0, c1, f1, cq, vy);
+        }
+    }
+    // ---- store wrapped x^(n+1) (and u)
+    if (MODE == MODE_FUSED) {
+        R *uo[3] = {(R *)sp.u[0], (R *)sp.u[1], (R *)sp.u[2]};
+#pragma unroll
+        for (int d = 0; d < 3; ++d) uo[d][i] = u[d];
+    }
+    if constexpr (P::PREC == 0) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            if (DIM == 2 && d == 1) continue;
+            double x = (double)c1[d] + f1[d];
+            const double L = (double)b.n[d];
+            if (x >= L) x -= L;
+            if (x < 0.0) x += L;
+            if (x >= L) x = 0.0;
+            sp.x[d][i] = x;
+        }
+    } else if (MODE == MODE_FUSED) {
+        int cw[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            if (DIM == 2 && d == 1) { cw[d] = 0; continue; }
+            cw[d] = wrap_index(c1[d], b.n[d]);
+            sp.off[d][i] = f1[d];
+        }
+        sp.cell[i] = cw[0] + b.n[0] * (cw[1] + b.n[1] * cw[2]);
+    }
+}
+
+// ------------------------------------------------------------ direct
+
+template <class P, int MODE>
+__global__ void __launch_bounds__(256) k_direct(KParams prm, int s) {
+    const DevSpecies &sp = prm.species[s];
+    const DevBox &b = prm.boxes[sp.box];
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= sp.np) return;
+    using FL = LdsField<typename P::FieldT>;
+    using JL = LdsJ<typename P::Acc>;
+    if (b.dim == 3)
+        particle<3, P, MODE, FL, JL>(b, sp, i, prm.f, nullptr, nullptr, nullptr, prm.err);
+    else
+        particle<2, P, MODE, FL, JL>(b, sp, i, prm.f, nullptr, nullptr, nullptr, prm.err);
+}
+
+// ------------------------------------------------------------ tiled / batched
+
+template <int DIM, class P, int MODE>
+__device__ void process_item(const KParams &prm, const Item &it, char *smem) {
+    using FT = typename P::FieldT;
+    using A = typename P::Acc;
+    const DevSpecies &sp = prm.species[it.s];
+    const DevBox &b = prm.boxes[sp.box];
+    Tile tile;
+    {
+        int t = it.t;
+        int tx = t % b.nt[0];
+        int ty = (t / b.nt[0]) % b.nt[1];
+        int tz = t / (b.nt[0] * b.nt[1]);
+        int tc[3] = {tx, ty, tz};
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            tile.t0[d] = tc[d] * b.tile[d];
+            tile.te[d] = min(b.tile[d], b.n[d] - tile.t0[d]);
+        }
+    }
+    const bool any = b.small != 0;
+    LdsField<FT> lf;
+    LdsJ<A> lj;
+    // field region: cells [t0 - GL, t0 + te + GH) per active axis
+    lf.base = (const FT *)smem;
+    lf.o0 = tile.t0[0] - H::GL; lf.L0 = tile.te[0] + H::GL + H::GH;
+    lf.o2 = tile.t0[2] - H::GL;
+    int L2 = tile.te[2] + H::GL + H::GH;
+    if (DIM == 3) { lf.o1 = tile.t0[1] - H::GL; lf.L1 = tile.te[1] + H::GL + H::GH; }
+    else { lf.o1 = 0; lf.L1 = 1; }
+    lf.L012 = lf.L0 * lf.L1 * L2;
+    // current region: nodes [t0 - JL, t0 + te + JH) per active axis
+    lj.base = (A *)(smem + prm.lds_field_bytes);
+    lj.o0 = tile.t0[0] - H::JL; lj.M0 = tile.te[0] + H::JL + H::JH;
+    lj.o2 = tile.t0[2] - H::JL;
+    int M2 = tile.te[2] + H::JL + H::JH;
+    if (DIM == 3) { lj.o1 = tile.t0[1] - H::JL; lj.M1 = tile.te[1] + H::JL + H::JH; }
+    else { lj.o1 = 0; lj.M1 = 1; }
+    lj.M012 = lj.M0 * lj.M1 * M2;
+
+    const int tid = threadIdx.x, bs = blockDim.x;
+    if (MODE & MODE_PUSH) {
+        FT *dst = (FT *)smem;
+        const int n = 6 * lf.L012;
+        for (int idx = tid; idx < n; idx += bs) {
+            int comp = idx / lf.L012;
+            int r = idx - comp * lf.L012;
+            int li = r % lf.L0;
+            int rr = r / lf.L0;
+            int lj_ = rr % lf.L1;
+            int lk = rr / lf.L1;
+            int gi = lf.o0 + li, gj = lf.o1 + lj_, gk = lf.o2 + lk;
+            if (any) { gi = wrap_index_any(gi, b.n[0]); gj = wrap_index_any(gj, b.n[1]); gk = wrap_index_any(gk, b.n[2]); }
+            else { gi = wrap_index(gi, b.n[0]); gj = wrap_index(gj, b.n[1]); gk = wrap_index(gk, b.n[2]); }
+            const FT *src = (const FT *)(comp < 3 ? prm.f.E[comp] : prm.f.B[comp - 3]);
+            dst[idx] = src[b.cell_base + gi + (long long)b.n[0] * (gj + (long long)b.n[1] * gk)];
+        }
+    }
+    if (MODE & MODE_DEPOSIT) {
+        const int n = 3 * lj.M012;
+        for (int idx = tid; idx < n; idx += bs) lj.base[idx] = A(0);
+    }
+    __syncthreads();
+    for (int p = it.p0 + tid; p < it.p1; p += bs)
+        particle<DIM, P, MODE>(b, sp, (long long)p, prm.f, &tile, &lf, &lj, prm.err);
+    __syncthreads();
+    if (MODE & MODE_DEPOSIT) {
+        const int n = 3 * lj.M012;
+        for (int idx = tid; idx < n; idx += bs) {
+            A v = lj.base[idx];
+            if (v == A(0)) continue;
+            int comp = idx / lj.M012;
+            int r = idx - comp * lj.M012;
+            int li = r % lj.M0;
+            int rr = r / lj.M0;
+            int ljj = rr % lj.M1;
+            int lk = rr / lj.M1;
+            int gi = lj.o0 + li, gj = lj.o1 + ljj, gk = lj.o2 + lk;
+            if (any) { gi = wrap_index_any(gi, b.n[0]); gj = wrap_index_any(gj, b.n[1]); gk = wrap_index_any(gk, b.n[2]); }
+            else { gi = wrap_index(gi, b.n[0]); gj = wrap_index(gj, b.n[1]); gk = wrap_index(gk, b.n[2]); }
+            unsafeAtomicAdd(&prm.f.J[comp][b.cell_base + gi + (long long)b.n[0] * (gj + (long long)b.n[1] * gk)],
+                            (double)v);
+        }
+    }
+    __syncthreads();
+}
+
+template <class P, int MODE, bool PERSISTENT>
+__global__ void __launch_bounds__(512) k_tiled(KParams prm) {
+    extern __shared__ __attribute__((aligned(16))) char smem[];
+    __shared__ Item cur;
+    for (int round = 0;; ++round) {
+        Item it;
+        if (PERSISTENT) {
+            if (threadIdx.x == 0) {
+                int idx = atomicAdd(prm.queue, 1);
+                cur = idx < *prm.nitems ? prm.items[idx] : Item{-1, 0, 0, 0};
+            }
+            __syncthreads();
+            it = cur;
+            __syncthreads();
+            if (it.s < 0) return;
+        } else {
+            if (round > 0) return;
+            const int bidx = blockIdx.x;
+            int s = 0;
+            while (s + 1 < prm.nsp && prm.sp_tile_prefix[s + 1] <= bidx) ++s;
+            const int t = bidx - prm.sp_tile_prefix[s];
+            const int *off = prm.species[s].tile_off;
+            it = Item{s, t, off[t], off[t + 1]};
+        }
+        if (it.p1 <= it.p0) continue;
+        const DevBox &b = prm.boxes[prm.species[it.s].box];
+        if (b.dim == 3) process_item<3, P, MODE>(prm, it, smem);
+        else process_item<2, P, MODE>(prm, it, smem);
+    }
+}
+
+template <class P, int MODE>
+hipError_t launch_mode(const KParams &prm, int form, int grid, int block, size_t lds,
+                       int species, hipStream_t st) {
+    if (form == 0) {
+        hipLaunchKernelGGL((k_direct<P, MODE>), dim3(grid), dim3(256), 0, st, prm, species);
+    } else if (form == 1) {
+        hipLaunchKernelGGL((k_tiled<P, MODE, false>), dim3(grid), dim3(block), lds, st, prm);
+    } else {
+        hipLaunchKernelGGL((k_tiled<P, MODE, true>), dim3(grid), dim3(block), lds, st, prm);
+    }
+    return hipGetLastError();
+}
+
+template <class P>
+hipError_t launch_prec(const KParams &prm, int form, int mode, int grid, int block,
+                       size_t lds, int species, hipStream_t st) {
+    if (mode == MODE_PUSH) return launch_mode<P, MODE_PUSH>(prm, form, grid, block, lds, species, st);
+    if (mode == MODE_DEPOSIT) return launch_mode<P, MODE_DEPOSIT>(prm, form, grid, block, lds, species, st);
+    return launch_mode<P, MODE_FUSED>(prm, form, grid, block, lds, species, st);
+}
+
+template <class P>
+hipError_t lds_limit_prec(int bytes) {
+    hipError_t e = hipSuccess;
+#define PIC_SET(M)                                                                                  \
+    if (e == hipSuccess)                                                                            \
+        e = hipFuncSetAttribute((const void *)&k_tiled<P, M, false>,                              \
+                                hipFuncAttributeMaxDynamicSharedMemorySize, bytes);                 \
+    if (e == hipSuccess)                                                                            \
+        e = hipFuncSetAttribute((const void *)&k_tiled<P, M, true>,                               \
+                                hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    PIC_SET(MODE_PUSH)
+    PIC_SET(MODE_DEPOSIT)
+    PIC_SET(MODE_FUSED)
+#undef PIC_SET
+    return e;
+}
+
+// Charge density on nodes (FP64, a check): rho += q w S S S / dV.
+template <class P>
+__global__ void k_rho(KParams prm, int s, double *rho) {
+    const DevSpecies &sp = prm.species[s];
+    const DevBox &b = prm.boxes[sp.box];
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= sp.np) return;
+    int c[3];
+    double f[3];
+    bool ok;
+    if constexpr (P::PREC == 0) {
+        ok = P::load(b, sp.x, i, c, f);
+    } else {
+        float ff[3];
+        ok = P::load(b, sp.cell, sp.off, i, c, ff);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) f[d] = (double)ff[d];
+    }
+    if (!ok) { flag_range(prm.err); return; }
+    GWin<O, double> g[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        if (b.dim == 2 && d == 1) {
+            g[d].base = 0;
+            for (int m = 0; m <= O; ++m) g[d].w[m] = (m == 0) ? 1.0 : 0.0;
+            continue;
+        }
+        g[d] = gather_window<O, double>(c[d], f[d], 0);
+    }
+    const double qw = sp.q * ((const typename P::R *)sp.w)[i] / (b.dx[0] * b.dx[1] * b.dx[2]);
+    const int ny = (b.dim == 2) ? 1 : O + 1;
+    for (int kk = 0; kk <= O; ++kk)
+        for (int jj = 0; jj < ny; ++jj)
+            for (int ii = 0; ii <= O; ++ii) {
+                double v = qw * g[0].w[ii] * g[1].w[jj] * g[2].w[kk];
+                if (v == 0.0) continue;
+                int a = wrap_index_any(g[0].base + ii, b.n[0]);
+                int bb = wrap_index_any(g[1].base + jj, b.n[1]);
+                int cc = wrap_index_any(g[2].base + kk, b.n[2]);
+                unsafeAtomicAdd(&rho[a + (long long)b.n[0] * (bb + (long long)b.n[1] * cc)], v);
+            }
+}
+
+}  // namespace
+
+#define PIC_CAT2(a, b) a##b
+#define PIC_CAT(a, b) PIC_CAT2(a, b)
+
+hipError_t PIC_CAT(launch_particles_o, PIC_ORDER)(const KParams &prm, int prec, int form, int mode,
+                                                 int grid, int block, size_t lds, int species,
+                                                 hipStream_t st) {
+    if (prec == 0) return launch_prec<F64>(prm, form, mode, grid, block, lds, species, st);
+    return launch_prec<Split>(prm, form, mode, grid, block, lds, species, st);
+}
+
+hipError_t PIC_CAT(particles_lds_limit_o, PIC_ORDER)(int prec, int bytes) {
+    if (prec == 0) return lds_limit_prec<F64>(bytes);
+    return lds_limit_prec<Split>(bytes);
+}
+
+}  // namespace pic
+
+namespace pic {
+hipError_t PIC_CAT(launch_rho_o, PIC_ORDER)(const KParams &prm, int prec, int species, long long np,
+                                           double *rho, hipStream_t st) {
+    if (np == 0) return hipSuccess;
+    dim3 g((unsigned)((np + 255) / 256)), bl(256);
+    if (prec == 0) hipLaunchKernelGGL(k_rho<F64>, g, bl, 0, st, prm, species, rho);
+    else hipLaunchKernelGGL(k_rho<Split>, g, bl, 0, st, prm, species, rho);
+    return hipGetLastError();
+}
+}  // namespace pic
