@@ -168,7 +168,7 @@ def main():
     ap.add_argument("--workload", default="c5", choices=["c5", "c2", "c4", "c1", "c3"])
     ap.add_argument("--sort-every", type=int, default=8)
     ap.add_argument("--tile32", type=int, nargs=3, default=(8, 8, 8))
-    ap.add_argument("--tile64", type=int, nargs=3, default=(8, 8, 8))
+    ap.add_argument("--tile64", type=int, nargs=3, default=(4, 4, 4))
     ap.add_argument("--block", type=int, default=256)
     ap.add_argument("--chunk", type=int, default=4096)
     ap.add_argument("--wg-per-cu", type=int, default=2)

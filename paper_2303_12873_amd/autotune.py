@@ -1,0 +1,137 @@
+"""Autotuner of the batched particle kernel: tile edge, workgroup size,
+particles per work item and persistent workgroups per CU.
+
+Every candidate runs the same inputs for a few whole steps through the C ABI
+(its own context, its own copy of the particles); candidates whose fields
+disagree with the first candidate's beyond the precision's tolerance are
+rejected, the fastest survivor is returned and cached as JSON keyed by the
+device name and a hash of the workload shape.
+"""
+from __future__ import annotations
+
+import hashlib
+import itertools
+import json
+import os
+import time
+from dataclasses import dataclass, asdict
+from typing import List, Optional
+
+import torch
+
+import paper_2303_12873_amd as pic
+
+DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "libpic_tuning.json")
+
+
+@dataclass
+class Candidate:
+    tile: tuple
+    block: int
+    chunk: int
+    wg_per_cu: int
+
+    def key(self):
+        return f"t{self.tile}-b{self.block}-c{self.chunk}-w{self.wg_per_cu}"
+
+
+def default_space(dim3: bool):
+    tiles = [(4, 4, 4), (8, 8, 8), (8, 8, 4)] if dim3 else [(8, 1, 8), (16, 1, 16), (8, 1, 16)]
+    blocks = [128, 256, 512]
+    chunks = [1024, 4096]
+    wgs = [1, 2, 4]
+    return [Candidate(t, b, c, w) for t, b, c, w in itertools.product(tiles, blocks, chunks, wgs)]
+
+
+def workload_key(wl, precision) -> str:
+    h = hashlib.sha1()
+    for b in wl.boxes:
+        h.update(repr((b.dim, b.n, b.order)).encode())
+    h.update(repr(([p.np for p in wl.species], precision)).encode())
+    return h.hexdigest()[:16]
+
+
+def _retile(boxes, tile):
+    import pic_inputs as pi
+    return [pi.Box(b.dim, b.n, b.dt, b.order,
+                   tuple(tile) if b.dim == 3 else (tile[0], 1, tile[2]), b.dx) for b in boxes]
+
+
+def _run(wl, precision, cand: Candidate, steps: int, sort_every: int, stream):
+    boxes = _retile(wl.boxes, cand.tile)
+    with torch.cuda.stream(stream):
+        ctx = pic.pic_init(boxes, precision, stream=stream.cuda_stream,
+                           kernel=pic.PIC_KERNEL_BATCHED, block=cand.block, chunk=cand.chunk,
+                           wg_per_cu=cand.wg_per_cu)
+        f = pic.make_fields(boxes, wl.E, wl.B, precision)
+        sp = [pic.make_species(p, precision) for p in wl.species]
+    try:
+        pic.pic_step(ctx, f, sp, sort=True)          # record + warm
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for k in range(steps):
+            pic.pic_step(ctx, f, sp, sort=((k + 1) % sort_every == 0))
+        e1.record(stream)
+        torch.cuda.synchronize()
+        pic.pic_check(ctx)
+        ms = e0.elapsed_time(e1) / steps
+        J = f.J.double().clone()
+        E = f.E.double().clone()
+    finally:
+        pic.pic_free(ctx)
+    return ms, E, J
+
+
+def tune(wl, precision=pic.PIC_FP32_SPLIT, space: Optional[List[Candidate]] = None,
+         steps: int = 3, sort_every: int = 4, budget_s: float = 120.0,
+         cache: Optional[str] = DEFAULT_CACHE, log=print):
+    """Returns (best Candidate, table of (key, ms or reason))."""
+    dim3 = all(b.dim == 3 for b in wl.boxes)
+    space = space or default_space(dim3)
+    wkey = f"{torch.cuda.get_device_name(0)}|{workload_key(wl, precision)}"
+    if cache and os.path.exists(cache):
+        try:
+            db = json.load(open(cache))
+            if wkey in db:
+                c = db[wkey]["best"]
+                return Candidate(tuple(c["tile"]), c["block"], c["chunk"], c["wg_per_cu"]), db[wkey]["table"]
+        except (OSError, ValueError, KeyError):
+            pass
+    tol = 1e-12 if precision == pic.PIC_FP64 else 1e-5
+    stream = torch.cuda.Stream()
+    ref = None
+    table = []
+    best, best_ms = None, float("inf")
+    t0 = time.time()
+    for cand in space:
+        if time.time() - t0 > budget_s:
+            table.append((cand.key(), "skipped: budget"))
+            continue
+        try:
+            ms, E, J = _run(wl, precision, cand, steps, sort_every, stream)
+        except pic.PicError as e:
+            table.append((cand.key(), f"rejected: {e}"))
+            continue
+        if ref is None:
+            ref = (E, J)
+        else:
+            err = max(float((E - ref[0]).norm() / ref[0].norm().clamp_min(1e-300)),
+                      float((J - ref[1]).norm() / ref[1].norm().clamp_min(1e-300)))
+            if err > tol:
+                table.append((cand.key(), f"rejected: parity {err:.2e}"))
+                continue
+        table.append((cand.key(), ms))
+        log(f"  {cand.key()}: {ms:.3f} ms/step")
+        if ms < best_ms:
+            best, best_ms = cand, ms
+    if best is not None and cache:
+        try:
+            os.makedirs(os.path.dirname(cache), exist_ok=True)
+            db = json.load(open(cache)) if os.path.exists(cache) else {}
+            db[wkey] = {"best": asdict(best), "table": table}
+            json.dump(db, open(cache, "w"), indent=1)
+        except (OSError, ValueError):
+            pass
+    return best, table

@@ -75,11 +75,12 @@ class Particles:
                          self.off.to(device), self.box)
 
     def numpy(self):
-        """Object with numpy float64 x, u, w (what the oracle consumes)."""
+        """Independent numpy float64 copies of x, u, w (what the oracle
+        consumes and updates in place)."""
         return SimpleSpecies(self.q, self.m,
-                             np.ascontiguousarray(self.x.cpu().numpy()),
-                             np.ascontiguousarray(self.u.cpu().numpy()),
-                             np.ascontiguousarray(self.w.cpu().numpy()))
+                             np.array(self.x.cpu().numpy(), dtype=np.float64, order="C", copy=True),
+                             np.array(self.u.cpu().numpy(), dtype=np.float64, order="C", copy=True),
+                             np.array(self.w.cpu().numpy(), dtype=np.float64, order="C", copy=True))
 
     def select(self, idx: torch.Tensor) -> "Particles":
         return Particles(self.q, self.m, self.x[:, idx].contiguous(),

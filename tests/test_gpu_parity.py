@@ -311,3 +311,25 @@ def test_empty_species_and_tiny_box():
         E, B, J = run.fields_np()
         assert rel_l2(J, Jo) <= tol and rel_l2(E, Eo) <= tol, (prec, rel_l2(J, Jo))
         run.free()
+
+
+@pytest.mark.parametrize("prec,tol", ((pic.PIC_FP64, TOL64), (pic.PIC_FP32_SPLIT, TOL32)))
+def test_batched_many_boxes_small_c4(prec, tol):
+    """Small copy of the batched workload: several 2D boxes of uneven size
+    and ppc plus a 3D box with lognormal tile counts, one persistent launch
+    per step, each box checked against its own oracle run."""
+    wl = pi.c4("cpu", nboxes=5, l_range=(12, 40), big=(32, 32, 32), mean_tile=64, sigma=1.5,
+               shell_radius=8.0)
+    refs = []
+    for b, (box, p) in enumerate(zip(wl.boxes, wl.species)):
+        sub = pi.Workload("box", [box], [p], [wl.E[b]], [wl.B[b]])
+        refs.append(_oracle_steps(sub, 2))
+    run = GpuRun(wl, prec, kernel=pic.PIC_KERNEL_BATCHED, chunk=50)
+    run.step(sort=True)
+    run.step(sort=False)
+    run.check()
+    for b, (Eo, Bo, Jo, sps) in enumerate(refs):
+        E, B, J = run.fields_np(b)
+        assert rel_l2(J, Jo) <= tol, (b, rel_l2(J, Jo))
+        assert rel_l2(E, Eo) <= tol and rel_l2(B, Bo) <= tol, b
+    run.free()
