@@ -56,7 +56,7 @@ def build_workload(name, device):
     raise SystemExit(f"unknown workload {name}")
 
 
-def run_form(wl, precision, kernel, steps, warmup, sort_every, tile, block, chunk, wg):
+def run_form(wl, precision, kernel, steps, warmup, sort_every, tile, block, chunk, wg, stride):
     import torch
     import paper_2303_12873_amd as pic
     import pic_inputs as pi
@@ -66,7 +66,7 @@ def run_form(wl, precision, kernel, steps, warmup, sort_every, tile, block, chun
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         ctx = pic.pic_init(boxes, precision, stream=stream.cuda_stream, kernel=kernel,
-                           block=block, chunk=chunk, wg_per_cu=wg)
+                           block=block, chunk=chunk, wg_per_cu=wg, lane_stride=stride)
         f = pic.make_fields(boxes, wl.E, wl.B, precision)
         sp = [pic.make_species(p, precision) for p in wl.species]
     torch.cuda.synchronize()
@@ -168,8 +168,10 @@ def main():
     ap.add_argument("--workload", default="c5", choices=["c5", "c2", "c4", "c1", "c3"])
     ap.add_argument("--sort-every", type=int, default=8)
     ap.add_argument("--tile32", type=int, nargs=3, default=(8, 8, 8))
-    ap.add_argument("--tile64", type=int, nargs=3, default=(4, 4, 4))
-    ap.add_argument("--block", type=int, default=256)
+    ap.add_argument("--tile64", type=int, nargs=3, default=(8, 8, 4))
+    ap.add_argument("--block", type=int, default=512)
+    ap.add_argument("--block64", type=int, default=256)
+    ap.add_argument("--stride", type=int, default=4, help="lane stride (particles per cell per species)")
     ap.add_argument("--chunk", type=int, default=4096)
     ap.add_argument("--wg-per-cu", type=int, default=2)
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison form")
@@ -197,13 +199,13 @@ def main():
 
     log("FP32 split + batched form")
     r32 = run_form(wl, pic.PIC_FP32_SPLIT, pic.PIC_KERNEL_BATCHED, args.steps, args.warmup,
-                   args.sort_every, args.tile32, args.block, args.chunk, args.wg_per_cu)
+                   args.sort_every, args.tile32, args.block, args.chunk, args.wg_per_cu, args.stride)
     log(f"  {r32}")
     r64 = None
     if not args.no_fp64:
         log("FP64 plain (tiled) form")
         r64 = run_form(wl, pic.PIC_FP64, pic.PIC_KERNEL_TILED, max(3, args.steps // 4), 1,
-                       args.sort_every, args.tile64, args.block, 0, 0)
+                       args.sort_every, args.tile64, args.block64, 0, 0, args.stride)
         log(f"  {r64}")
 
     value = r32["np"] * 1e3 / r32["ms_step"]
@@ -234,7 +236,7 @@ def main():
         "config": {"workload": wl.name, "cells": ncells, "particles": r32["np"], "order": order,
                    "form": "fp32_split_batched_graph", "sort_every": args.sort_every,
                    "tile": list(args.tile32), "block": args.block, "chunk": args.chunk,
-                   "wg_per_cu": args.wg_per_cu},
+                   "wg_per_cu": args.wg_per_cu, "lane_stride": args.stride},
         "roofline": roof,
         "breakdown_ms": {"advance": r32["ms_advance"], "sort": r32["ms_sort"],
                          "fdtd": r32["ms_fdtd"]},

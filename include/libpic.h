@@ -63,8 +63,13 @@ typedef enum {
     PIC_KERNEL_DIRECT = 0,  /* one thread per particle, fields and J in global
                                memory (no sort needed) */
     PIC_KERNEL_TILED = 1,   /* one workgroup per (species, tile): E/B staged
-                               in LDS, J accumulated in LDS then flushed with
-                               FP64 global atomics (needs pic_sort_tiles) */
+                               in LDS, J accumulated in an FP64 LDS tile then
+                               flushed with FP64 global atomics (needs
+                               pic_sort_tiles).  The staged region carries a
+                               1-cell margin when it fits in LDS, so particles
+                               that drifted up to one cell out of their tile
+                               since the sort stay on the LDS path; beyond
+                               that they use global memory. */
     PIC_KERNEL_BATCHED = 2  /* as TILED, but a persistent grid walks a work
                                queue of (species, tile, chunk) items so uneven
                                tiles and many boxes share one launch */
@@ -87,6 +92,10 @@ typedef struct {
                             (64..512, multiple of 64; 0 = default 256) */
     int32_t chunk;       /* BATCHED: max particles per work item (0 = 4096) */
     int32_t wg_per_cu;   /* BATCHED: persistent workgroups per CU (0 = 2) */
+    int32_t lane_stride; /* TILED/BATCHED: lane l of a work item's pass takes
+                            particle (l mod G)*stride + l/G, G = ceil(n/stride),
+                            so lanes of one wave fall in distinct cells when
+                            stride ~ particles per cell (1..64; 0 = 1) */
 } pic_tuning;
 
 typedef struct {

@@ -12,7 +12,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/libpic.h"
+#include "libpic.h"
 #include "pic_aux.h"
 #include "pic_dev.h"
 #include "pic_math.h"
@@ -92,6 +92,7 @@ struct pic_ctx {
     long long total_cells = 0;
     int *derr = nullptr;
     size_t lds_field_bytes = 0, lds_bytes = 0;
+    int margin = 0;                 // cells staged around each tile
     // species
     std::vector<Slot> slots;
     std::vector<DevSpecies> hsp;    // last uploaded table
@@ -303,6 +304,8 @@ KParams make_params(pic_ctx *c, const pic_fields *f, int nsp) {
     k.nitems = c->nitems;
     k.queue = c->queue;
     k.lds_field_bytes = (int)c->lds_field_bytes;
+    k.lane_stride = c->tun.lane_stride;
+    k.margin = c->margin;
     return k;
 }
 
@@ -536,16 +539,19 @@ pic_status pic_init(pic_ctx **out, const pic_box_desc *boxes, int32_t nboxes, pi
     t.block = 256;
     t.chunk = 4096;
     t.wg_per_cu = 2;
+    t.lane_stride = 1;
     if (tuning) {
         t.kernel = tuning->kernel;
         if (tuning->block) t.block = tuning->block;
         if (tuning->chunk) t.chunk = tuning->chunk;
         if (tuning->wg_per_cu) t.wg_per_cu = tuning->wg_per_cu;
+        if (tuning->lane_stride) t.lane_stride = tuning->lane_stride;
     }
     if (t.kernel < 0 || t.kernel > 2) return fail(PIC_ERR_ARG, "bad kernel form");
     if (t.block < 64 || t.block > 512 || t.block % 64) return fail(PIC_ERR_ARG, "block must be 64..512, multiple of 64");
     if (t.chunk < 1) return fail(PIC_ERR_ARG, "chunk must be >= 1");
     if (t.wg_per_cu < 1 || t.wg_per_cu > 64) return fail(PIC_ERR_ARG, "wg_per_cu must be 1..64");
+    if (t.lane_stride < 1 || t.lane_stride > 64) return fail(PIC_ERR_ARG, "lane_stride must be 1..64");
 
     pic_ctx *c = new pic_ctx();
     c->nboxes = nboxes;
@@ -561,7 +567,7 @@ pic_status pic_init(pic_ctx **out, const pic_box_desc *boxes, int32_t nboxes, pi
     }
     const int o = c->order;
     const size_t fb = prec == PIC_FP64 ? 8 : 4;
-    size_t fmax = 0, jmax = 0;
+    size_t fmax = 0, jmax = 0, fmax1 = 0, jmax1 = 0;   // without / with a 1-cell margin
     c->hfp.assign(nboxes + 1, 0);
     for (int i = 0; i < nboxes; ++i) {
         const pic_box_desc &b = boxes[i];
@@ -571,7 +577,8 @@ pic_status pic_init(pic_ctx **out, const pic_box_desc *boxes, int32_t nboxes, pi
         d.order = b.order;
         d.ncells = 1;
         d.small = 0;
-        size_t fr = 6 * fb, jr = 3 * fb;
+        size_t fr = 6 * fb, jr = 3 * 8;   // the LDS current tile is FP64 in both forms
+        size_t fr1 = fr, jr1 = jr;
         for (int k = 0; k < 3; ++k) {
             d.n[k] = b.n[k];
             d.tile[k] = b.tile[k];
@@ -583,18 +590,30 @@ pic_status pic_init(pic_ctx **out, const pic_box_desc *boxes, int32_t nboxes, pi
                 int te = std::min(b.tile[k], b.n[k]);
                 fr *= (size_t)(te + halo_gl(o) + halo_gh(o));
                 jr *= (size_t)(te + halo_jl(o) + halo_jh(o));
+                fr1 *= (size_t)(te + halo_gl(o) + halo_gh(o) + 2);
+                jr1 *= (size_t)(te + halo_jl(o) + halo_jh(o) + 2);
                 if (b.n[k] < 8) d.small = 1;
             }
         }
         d.ntiles = d.nt[0] * d.nt[1] * d.nt[2];
         d.cell_base = b.cell_base;
         d.dt = b.dt;
+        d.inv_nx = 1.0 / (double)b.n[0];
+        d.inv_nxy = 1.0 / ((double)b.n[0] * (double)b.n[1]);
         fmax = std::max(fmax, fr);
         jmax = std::max(jmax, jr);
+        fmax1 = std::max(fmax1, fr1);
+        jmax1 = std::max(jmax1, jr1);
         c->hbox.push_back(d);
         c->hfp[i + 1] = c->hfp[i] + d.ncells;
     }
     c->total_cells = c->hfp[nboxes];
+    // Stage a 1-cell margin around every tile when it fits in LDS.
+    if ((fmax1 + 15) / 16 * 16 + jmax1 <= (size_t)LDS_BYTES_MAX) {
+        c->margin = 1;
+        fmax = fmax1;
+        jmax = jmax1;
+    }
     c->lds_field_bytes = (fmax + 15) / 16 * 16;
     c->lds_bytes = c->lds_field_bytes + jmax;
     if (t.kernel != PIC_KERNEL_DIRECT && c->lds_bytes > (size_t)LDS_BYTES_MAX) {

@@ -21,6 +21,7 @@ struct DevBox {
     long long ncells;
     double dt;
     double dx[3];
+    double inv_nx, inv_nxy;   // 1/n[0], 1/(n[0] n[1]) for index decoding
 };
 
 struct DevSpecies {
@@ -69,6 +70,8 @@ struct KParams {
     const int *nitems;
     int *queue;
     int lds_field_bytes;      // offset of the J region in dynamic LDS
+    int lane_stride;          // lane -> particle stride inside a work item
+    int margin;               // cells staged around each tile (0 or 1)
 };
 
 }  // namespace pic

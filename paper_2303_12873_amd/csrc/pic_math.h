@@ -167,9 +167,9 @@ __device__ inline DWin<O, R> deposit_window(int c0u, R f0u, int c1u, R f1u) {
     return d;
 }
 
-// Node range [lo, hi] (relative to the particle's cell) that the gather
-// windows of all six Yee components can touch, and that the deposit window
-// can touch for any move of less than one cell.
+// Node range [c - GL, c + GH] (relative to the particle's cell c) that the
+// gather windows of all six Yee components can touch, and [c - JL, c + JH]
+// that the deposit window can touch for any move of less than one cell.
 template <int O> struct Halo;
 template <> struct Halo<1> { static constexpr int GL = 1, GH = 1, JL = 1, JH = 2; };
 template <> struct Halo<2> { static constexpr int GL = 1, GH = 2, JL = 2, JH = 3; };

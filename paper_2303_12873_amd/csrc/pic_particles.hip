@@ -17,7 +17,7 @@
 //
 // Precision policies: F64 (FP64 positions, momenta, fields, LDS J) and
 // Split (int32 cell + FP32 in-cell offset, FP32 momenta, fields, gather,
-// push, LDS J; J flushed to FP64).
+// push; current accumulated in an FP64 LDS tile, flushed to FP64 J).
 #include "pic_dev.h"
 #include "pic_math.h"
 #include "pic_aux.h"
@@ -57,19 +57,31 @@ struct F64 {
     }
 };
 
+// floor(a / d) for 0 <= a < 2^31, 1 <= d < 2^31, from an FP64 reciprocal:
+// the product is within one of the quotient, fixed by one correction step.
+__device__ inline int div_exact(int a, int d, double inv_d) {
+    int q = (int)((double)a * inv_d);
+    int r = a - q * d;
+    q += (r >= d) - (r < 0);
+    return q;
+}
+
+// The LDS current tile is FP64 in both forms: measured on gfx950, LDS FP32
+// atomic adds (ds_add_f32) ran ~6x slower than FP64 ones (ds_add_f64) on the
+// deposit's access pattern, and FP64 keeps the tile sum exact to 1e-16.
 struct Split {
     using R = float;
     using FieldT = float;
-    using Acc = float;
+    using Acc = double;
     static constexpr int PREC = 1;
     __device__ static bool load(const DevBox &b, const int *cells, float *const offs[3],
                                 long long i, int c[3], float f[3]) {
         int cell = cells[i];
         if (cell < 0 || (long long)cell >= b.ncells) return false;
-        int nx = b.n[0], nxy = b.n[0] * b.n[1];
-        c[2] = cell / nxy;
+        const int nx = b.n[0], nxy = b.n[0] * b.n[1];
+        c[2] = div_exact(cell, nxy, b.inv_nxy);
         int r = cell - c[2] * nxy;
-        c[1] = r / nx;
+        c[1] = div_exact(r, nx, b.inv_nx);
         c[0] = r - c[1] * nx;
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
@@ -191,8 +203,10 @@ __device__ inline void gather(const FA &fa, const int c[3], const R f[3], R E[3]
 
 // Esirkepov weights: W^x = dSx (S0y S0z + dSy S0z/2 + S0y dSz/2 + dSy dSz/3)
 // and cyclically; J along an axis is the running sum of its W over the
-// window, scaled by -q w / (dt * face area).  The last edge of each line
-// carries the sum of all dS (zero) and is not written.
+// window, scaled by -q w / (dt * face area).  Since W^x factors into dSx_i
+// times a (j, k) term, the running sum is (sum_{i'<=i} dSx_i') times that
+// term: the scaled prefix sums are formed once per axis.  The last edge of
+// each line carries the sum of all dS (zero) and is not written.
 template <int DIM, typename R, class JA>
 __device__ inline void deposit(const JA &ja, const int c0[3], const R f0[3],
                                const int c1[3], const R f1[3], R cq[3], R vy) {
@@ -200,8 +214,26 @@ __device__ inline void deposit(const JA &ja, const int c0[3], const R f0[3],
     DWin<O, R> wx = deposit_window<O, R>(c0[0], f0[0], c1[0], f1[0]);
     DWin<O, R> wz = deposit_window<O, R>(c0[2], f0[2], c1[2], f1[2]);
     const R third = R(1.0 / 3.0);
+    // The products handed to the FP64 atomics are formed in FP64 from the
+    // prefix sums and line weights, so no per-atomic conversion is needed.
+    using A = double;
+    A px[K - 1], pz[K - 1];
+    {
+        R a = R(0), c = R(0);
+#pragma unroll
+        for (int i = 0; i < K - 1; ++i) {
+            a += wx.dS[i]; px[i] = (A)(cq[0] * a);
+            c += wz.dS[i]; pz[i] = (A)(cq[2] * c);
+        }
+    }
     if (DIM == 3) {
         DWin<O, R> wy = deposit_window<O, R>(c0[1], f0[1], c1[1], f1[1]);
+        A py[K - 1];
+        {
+            R a = R(0);
+#pragma unroll
+            for (int i = 0; i < K - 1; ++i) { a += wy.dS[i]; py[i] = (A)(cq[1] * a); }
+        }
 #pragma unroll
         for (int k = 0; k < K; ++k) {
 #pragma unroll
@@ -209,12 +241,8 @@ __device__ inline void deposit(const JA &ja, const int c0[3], const R f0[3],
                 R t = wy.S0[j] * wz.S0[k] + R(0.5) * (wy.dS[j] * wz.S0[k] + wy.S0[j] * wz.dS[k]) +
                       third * wy.dS[j] * wz.dS[k];
                 if (t == R(0)) continue;
-                R acc = R(0);
 #pragma unroll
-                for (int i = 0; i < K - 1; ++i) {
-                    acc += wx.dS[i] * t;
-                    ja.add(0, wx.base + i, wy.base + j, wz.base + k, cq[0] * acc);
-                }
+                for (int i = 0; i < K - 1; ++i) ja.add(0, wx.base + i, wy.base + j, wz.base + k, px[i] * (A)t);
             }
         }
 #pragma unroll
@@ -224,12 +252,8 @@ __device__ inline void deposit(const JA &ja, const int c0[3], const R f0[3],
                 R t = wz.S0[k] * wx.S0[i] + R(0.5) * (wz.dS[k] * wx.S0[i] + wz.S0[k] * wx.dS[i]) +
                       third * wz.dS[k] * wx.dS[i];
                 if (t == R(0)) continue;
-                R acc = R(0);
 #pragma unroll
-                for (int j = 0; j < K - 1; ++j) {
-                    acc += wy.dS[j] * t;
-                    ja.add(1, wx.base + i, wy.base + j, wz.base + k, cq[1] * acc);
-                }
+                for (int j = 0; j < K - 1; ++j) ja.add(1, wx.base + i, wy.base + j, wz.base + k, py[j] * (A)t);
             }
         }
 #pragma unroll
@@ -239,12 +263,8 @@ __device__ inline void deposit(const JA &ja, const int c0[3], const R f0[3],
                 R t = wx.S0[i] * wy.S0[j] + R(0.5) * (wx.dS[i] * wy.S0[j] + wx.S0[i] * wy.dS[j]) +
                       third * wx.dS[i] * wy.dS[j];
                 if (t == R(0)) continue;
-                R acc = R(0);
 #pragma unroll
-                for (int k = 0; k < K - 1; ++k) {
-                    acc += wz.dS[k] * t;
-                    ja.add(2, wx.base + i, wy.base + j, wz.base + k, cq[2] * acc);
-                }
+                for (int k = 0; k < K - 1; ++k) ja.add(2, wx.base + i, wy.base + j, wz.base + k, pz[k] * (A)t);
             }
         }
     } else {
@@ -252,32 +272,24 @@ __device__ inline void deposit(const JA &ja, const int c0[3], const R f0[3],
         for (int k = 0; k < K; ++k) {
             R t = wz.S0[k] + R(0.5) * wz.dS[k];
             if (t == R(0)) continue;
-            R acc = R(0);
 #pragma unroll
-            for (int i = 0; i < K - 1; ++i) {
-                acc += wx.dS[i] * t;
-                ja.add(0, wx.base + i, 0, wz.base + k, cq[0] * acc);
-            }
+            for (int i = 0; i < K - 1; ++i) ja.add(0, wx.base + i, 0, wz.base + k, px[i] * (A)t);
         }
 #pragma unroll
         for (int i = 0; i < K; ++i) {
             R t = wx.S0[i] + R(0.5) * wx.dS[i];
             if (t == R(0)) continue;
-            R acc = R(0);
 #pragma unroll
-            for (int k = 0; k < K - 1; ++k) {
-                acc += wz.dS[k] * t;
-                ja.add(2, wx.base + i, 0, wz.base + k, cq[2] * acc);
-            }
+            for (int k = 0; k < K - 1; ++k) ja.add(2, wx.base + i, 0, wz.base + k, pz[k] * (A)t);
         }
-        const R cy = cq[1] * vy;
+        const A cy = (A)(cq[1] * vy);
 #pragma unroll
         for (int k = 0; k < K; ++k) {
 #pragma unroll
             for (int i = 0; i < K; ++i) {
                 R a = wx.S0[i] * wz.S0[k] + R(0.5) * (wx.dS[i] * wz.S0[k] + wx.S0[i] * wz.dS[k]) +
                       third * wx.dS[i] * wz.dS[k];
-                if (a != R(0)) ja.add(1, wx.base + i, 0, wz.base + k, cy * a);
+                if (a != R(0)) ja.add(1, wx.base + i, 0, wz.base + k, cy * (A)a);
             }
         }
     }
@@ -285,11 +297,17 @@ __device__ inline void deposit(const JA &ja, const int c0[3], const R f0[3],
 
 // ------------------------------------------------------------ one particle
 
+// A tile's cells [t0, t0 + te) plus the staged margin of `mg` cells, so a
+// particle that drifted up to mg cells out of its tile since the last sort
+// still gathers and deposits through LDS.  In 2D the y range is the single
+// cell 0 and always holds.
 struct Tile {
     int t0[3], te[3];
+    int mg;
     __device__ inline bool holds(const int c[3]) const {
-        return c[0] >= t0[0] && c[0] < t0[0] + te[0] && c[1] >= t0[1] &&
-               c[1] < t0[1] + te[1] && c[2] >= t0[2] && c[2] < t0[2] + te[2];
+        return c[0] >= t0[0] - mg && c[0] < t0[0] + te[0] + mg &&
+               c[1] >= t0[1] - mg && c[1] < t0[1] + te[1] + mg &&
+               c[2] >= t0[2] - mg && c[2] < t0[2] + te[2] + mg;
     }
 };
 
@@ -506,6 +524,31 @@ __global__ void __launch_bounds__(256) k_direct(KParams prm, int s) {
 
 // ------------------------------------------------------------ tiled / batched
 
+// Walks the flattened (component, k, j, i) index of an LDS region, i
+// fastest, from `start` in steps of `stride`, with the coordinates updated
+// by carries instead of a division per element.
+struct RegionWalk {
+    int i, j, k, c;
+    int si, sj, sk, sc;
+    int L0, L1, L2;
+    __device__ RegionWalk(int start, int stride, int l0, int l1, int l2)
+        : L0(l0), L1(l1), L2(l2) {
+        decompose(start, i, j, k, c);
+        decompose(stride, si, sj, sk, sc);
+    }
+    __device__ void decompose(int x, int &a, int &b_, int &d, int &e) const {
+        a = x % L0; x /= L0;
+        b_ = x % L1; x /= L1;
+        d = x % L2; e = x / L2;
+    }
+    __device__ inline void next() {
+        i += si; int ci = i >= L0; i -= ci ? L0 : 0;
+        j += sj + ci; int cj = j >= L1; j -= cj ? L1 : 0;
+        k += sk + cj; int ck = k >= L2; k -= ck ? L2 : 0;
+        c += sc + ck;
+    }
+};
+
 template <int DIM, class P, int MODE>
 __device__ void process_item(const KParams &prm, const Item &it, char *smem) {
     using FT = typename P::FieldT;
@@ -530,18 +573,21 @@ __device__ void process_item(const KParams &prm, const Item &it, char *smem) {
     LdsJ<A> lj;
     // field region: cells [t0 - GL, t0 + te + GH) per active axis
     lf.base = (const FT *)smem;
-    lf.o0 = tile.t0[0] - H::GL; lf.L0 = tile.te[0] + H::GL + H::GH;
-    lf.o2 = tile.t0[2] - H::GL;
-    int L2 = tile.te[2] + H::GL + H::GH;
-    if (DIM == 3) { lf.o1 = tile.t0[1] - H::GL; lf.L1 = tile.te[1] + H::GL + H::GH; }
+    tile.mg = prm.margin;
+    const int GL = H::GL + tile.mg, GW = H::GL + H::GH + 2 * tile.mg;
+    lf.o0 = tile.t0[0] - GL; lf.L0 = tile.te[0] + GW;
+    lf.o2 = tile.t0[2] - GL;
+    int L2 = tile.te[2] + GW;
+    if (DIM == 3) { lf.o1 = tile.t0[1] - GL; lf.L1 = tile.te[1] + GW; }
     else { lf.o1 = 0; lf.L1 = 1; }
     lf.L012 = lf.L0 * lf.L1 * L2;
     // current region: nodes [t0 - JL, t0 + te + JH) per active axis
     lj.base = (A *)(smem + prm.lds_field_bytes);
-    lj.o0 = tile.t0[0] - H::JL; lj.M0 = tile.te[0] + H::JL + H::JH;
-    lj.o2 = tile.t0[2] - H::JL;
-    int M2 = tile.te[2] + H::JL + H::JH;
-    if (DIM == 3) { lj.o1 = tile.t0[1] - H::JL; lj.M1 = tile.te[1] + H::JL + H::JH; }
+    const int JL = H::JL + tile.mg, JW = H::JL + H::JH + 2 * tile.mg;
+    lj.o0 = tile.t0[0] - JL; lj.M0 = tile.te[0] + JW;
+    lj.o2 = tile.t0[2] - JL;
+    int M2 = tile.te[2] + JW;
+    if (DIM == 3) { lj.o1 = tile.t0[1] - JL; lj.M1 = tile.te[1] + JW; }
     else { lj.o1 = 0; lj.M1 = 1; }
     lj.M012 = lj.M0 * lj.M1 * M2;
 
@@ -549,17 +595,12 @@ __device__ void process_item(const KParams &prm, const Item &it, char *smem) {
     if (MODE & MODE_PUSH) {
         FT *dst = (FT *)smem;
         const int n = 6 * lf.L012;
-        for (int idx = tid; idx < n; idx += bs) {
-            int comp = idx / lf.L012;
-            int r = idx - comp * lf.L012;
-            int li = r % lf.L0;
-            int rr = r / lf.L0;
-            int lj_ = rr % lf.L1;
-            int lk = rr / lf.L1;
-            int gi = lf.o0 + li, gj = lf.o1 + lj_, gk = lf.o2 + lk;
+        RegionWalk w(tid, bs, lf.L0, lf.L1, L2);
+        for (int idx = tid; idx < n; idx += bs, w.next()) {
+            int gi = lf.o0 + w.i, gj = lf.o1 + w.j, gk = lf.o2 + w.k;
             if (any) { gi = wrap_index_any(gi, b.n[0]); gj = wrap_index_any(gj, b.n[1]); gk = wrap_index_any(gk, b.n[2]); }
             else { gi = wrap_index(gi, b.n[0]); gj = wrap_index(gj, b.n[1]); gk = wrap_index(gk, b.n[2]); }
-            const FT *src = (const FT *)(comp < 3 ? prm.f.E[comp] : prm.f.B[comp - 3]);
+            const FT *src = (const FT *)(w.c < 3 ? prm.f.E[w.c] : prm.f.B[w.c - 3]);
             dst[idx] = src[b.cell_base + gi + (long long)b.n[0] * (gj + (long long)b.n[1] * gk)];
         }
     }
@@ -568,24 +609,38 @@ __device__ void process_item(const KParams &prm, const Item &it, char *smem) {
         for (int idx = tid; idx < n; idx += bs) lj.base[idx] = A(0);
     }
     __syncthreads();
-    for (int p = it.p0 + tid; p < it.p1; p += bs)
-        particle<DIM, P, MODE>(b, sp, (long long)p, prm.f, &tile, &lf, &lj, prm.err);
+    // Lane -> particle map: slot s takes particle (s mod G) * S + s / G of
+    // the item (S = lane stride, G = ceil(n / S)), so that with S equal to
+    // the particles per cell the lanes of one wave sit in distinct cells and
+    // their LDS atomics do not collide on one address.  S = 1 is the
+    // identity.
+    {
+        const int n = it.p1 - it.p0;
+        const int S = prm.lane_stride > 1 ? prm.lane_stride : 1;
+        const int G = (n + S - 1) / S;
+        const int total = G * S;
+        int q = tid / G, r = tid - (tid / G) * G;
+        const int dq = bs / G, dr = bs - (bs / G) * G;
+        for (int sl = tid; sl < total; sl += bs) {
+            const int idx = r * S + q;
+            if (idx < n)
+                particle<DIM, P, MODE>(b, sp, (long long)(it.p0 + idx), prm.f, &tile, &lf, &lj, prm.err);
+            r += dr;
+            q += dq;
+            if (r >= G) { r -= G; q += 1; }
+        }
+    }
     __syncthreads();
     if (MODE & MODE_DEPOSIT) {
         const int n = 3 * lj.M012;
-        for (int idx = tid; idx < n; idx += bs) {
+        RegionWalk w(tid, bs, lj.M0, lj.M1, M2);
+        for (int idx = tid; idx < n; idx += bs, w.next()) {
             A v = lj.base[idx];
             if (v == A(0)) continue;
-            int comp = idx / lj.M012;
-            int r = idx - comp * lj.M012;
-            int li = r % lj.M0;
-            int rr = r / lj.M0;
-            int ljj = rr % lj.M1;
-            int lk = rr / lj.M1;
-            int gi = lj.o0 + li, gj = lj.o1 + ljj, gk = lj.o2 + lk;
+            int gi = lj.o0 + w.i, gj = lj.o1 + w.j, gk = lj.o2 + w.k;
             if (any) { gi = wrap_index_any(gi, b.n[0]); gj = wrap_index_any(gj, b.n[1]); gk = wrap_index_any(gk, b.n[2]); }
             else { gi = wrap_index(gi, b.n[0]); gj = wrap_index(gj, b.n[1]); gk = wrap_index(gk, b.n[2]); }
-            unsafeAtomicAdd(&prm.f.J[comp][b.cell_base + gi + (long long)b.n[0] * (gj + (long long)b.n[1] * gk)],
+            unsafeAtomicAdd(&prm.f.J[w.c][b.cell_base + gi + (long long)b.n[0] * (gj + (long long)b.n[1] * gk)],
                             (double)v);
         }
     }

@@ -284,12 +284,17 @@ def c3(device="cpu", fields=None) -> Workload:
 
 
 def lwfa_box(n, ppc, order, a0, species=("e",), seed=SEED0 + 1, device="cpu",
-             tile=(8, 8, 8), z_slab: Optional[Tuple[int, int]] = None) -> Workload:
+             tile=(8, 8, 8), z_slab: Optional[Tuple[int, int]] = None,
+             u_th: float = 0.01) -> Workload:
     """Laser-wakefield box: laser (lambda = 20 cells, waist 16, length 20,
     centroid z0 = 60, centred transversely) in vacuum below z = 120, plasma
-    ramp 120 -> 220 then n0 = 1e-3 n_c, ``ppc`` cold particles per cell
-    wherever n > 0 (weight n dV / ppc).  ``z_slab`` restricts the particles
-    to cell layers [z_lo, z_hi) (bounded samples of the same workload)."""
+    ramp 120 -> 220 then n0 = 1e-3 n_c, ``ppc`` particles per cell wherever
+    n > 0 (weight n dV / ppc).  The plasma temperature is not given by the
+    workload description; electrons get a thermal spread u_th (default
+    0.01 c, as the uniform boxes) and ions the same temperature
+    (u_th / sqrt(m_i/m_e)), so every particle moves from the first step.
+    ``z_slab`` restricts the particles to cell layers [z_lo, z_hi) (bounded
+    samples of the same workload)."""
     box = Box(3, tuple(n), DT3, order, tuple(tile))
     n0 = 1e-3 * N_CRIT
     k = torch.arange(box.n[2], dtype=torch.float64)
@@ -303,7 +308,7 @@ def lwfa_box(n, ppc, order, a0, species=("e",), seed=SEED0 + 1, device="cpu",
     sps = []
     for si, s in enumerate(species):
         q, m = (-1.0, 1.0) if s == "e" else (1.0, M_ION)
-        sps.append(particles_in_cells(box, cells, ppc, wcell, q, m, 0.0,
+        sps.append(particles_in_cells(box, cells, ppc, wcell, q, m, u_th / math.sqrt(m),
                                       seed + 100 * si, device))
     E, B = laser_fields(box, a0, 16.0, 20.0, 60.0, (box.n[0] / 2, box.n[1] / 2), device)
     return Workload("lwfa", [box], sps, [E], [B], 200)

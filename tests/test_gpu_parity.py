@@ -333,3 +333,25 @@ def test_batched_many_boxes_small_c4(prec, tol):
         assert rel_l2(J, Jo) <= tol, (b, rel_l2(J, Jo))
         assert rel_l2(E, Eo) <= tol and rel_l2(B, Bo) <= tol, b
     run.free()
+
+
+@pytest.mark.parametrize("prec,tol", ((pic.PIC_FP64, TOL64), (pic.PIC_FP32_SPLIT, TOL32)))
+@pytest.mark.parametrize("kernel,stride", (("tiled", 1), ("tiled", 3), ("batched", 8), ("batched", 4)))
+def test_lane_stride_margin_and_stale_sort(prec, tol, kernel, stride):
+    """Hot plasma, one sort then five steps: particles drift inside the
+    staged margin and some beyond it (global path); every lane mapping must
+    give the oracle's result."""
+    wl = pi.uniform_box((16, 12, 12), 5, 0.05, 0.35, 2, 1500, "cpu", tile=(4, 4, 4),
+                        fields="fourier")
+    Eo, Bo, Jo, sps = _oracle_steps(wl, 5)
+    run = GpuRun(wl, prec, kernel=KERNELS[kernel], chunk=61, lane_stride=stride)
+    run.sort()
+    for _ in range(5):
+        run.particles()
+        pic.pic_fdtd_step(run.ctx, run.f)
+    run.check()
+    E, B, J = run.fields_np()
+    assert rel_l2(J, Jo) <= tol and rel_l2(E, Eo) <= tol, (rel_l2(J, Jo), rel_l2(E, Eo))
+    x, u = run.state_np()
+    assert rel_l2(u, sps[0].u) <= tol
+    run.free()
