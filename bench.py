@@ -169,8 +169,8 @@ def main():
     ap.add_argument("--sort-every", type=int, default=8)
     ap.add_argument("--tile32", type=int, nargs=3, default=(8, 8, 8))
     ap.add_argument("--tile64", type=int, nargs=3, default=(8, 8, 4))
-    ap.add_argument("--block", type=int, default=512)
-    ap.add_argument("--block64", type=int, default=256)
+    ap.add_argument("--block", type=int, default=1024)
+    ap.add_argument("--block64", type=int, default=512)
     ap.add_argument("--stride", type=int, default=4, help="lane stride (particles per cell per species)")
     ap.add_argument("--chunk", type=int, default=4096)
     ap.add_argument("--wg-per-cu", type=int, default=2)

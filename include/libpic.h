@@ -88,14 +88,18 @@ typedef struct {
 
 typedef struct {
     int32_t kernel;      /* pic_kernel */
-    int32_t block;       /* threads per workgroup of particle kernels
-                            (64..512, multiple of 64; 0 = default 256) */
+    int32_t block;       /* threads per workgroup of the tiled kernels
+                            (multiple of 64; 64..512 for PIC_FP64, 64..1024
+                            for PIC_FP32_SPLIT; 0 = default 256) */
     int32_t chunk;       /* BATCHED: max particles per work item (0 = 4096) */
     int32_t wg_per_cu;   /* BATCHED: persistent workgroups per CU (0 = 2) */
     int32_t lane_stride; /* TILED/BATCHED: lane l of a work item's pass takes
                             particle (l mod G)*stride + l/G, G = ceil(n/stride),
                             so lanes of one wave fall in distinct cells when
                             stride ~ particles per cell (1..64; 0 = 1) */
+    int32_t pad;         /* 0: pad the row of the LDS current tile so a
+                            wave's lanes hit distinct LDS banks (when it
+                            fits); -1: no padding */
 } pic_tuning;
 
 typedef struct {

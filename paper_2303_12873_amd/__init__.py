@@ -38,7 +38,7 @@ class pic_box_desc(C.Structure):
 
 class pic_tuning(C.Structure):
     _fields_ = [("kernel", C.c_int32), ("block", C.c_int32), ("chunk", C.c_int32),
-                ("wg_per_cu", C.c_int32), ("lane_stride", C.c_int32)]
+                ("wg_per_cu", C.c_int32), ("lane_stride", C.c_int32), ("pad", C.c_int32)]
 
 
 class pic_fields(C.Structure):
@@ -207,7 +207,7 @@ def _ptr_array(ts):
 # ------------------------------------------------------------------ C ABI names
 
 def pic_init(boxes, precision: int, stream=None, kernel: Optional[int] = None, block: int = 0,
-             chunk: int = 0, wg_per_cu: int = 0, lane_stride: int = 0):
+             chunk: int = 0, wg_per_cu: int = 0, lane_stride: int = 0, pad: int = 0):
     """boxes: objects with dim, n, dx, dt, order, tile (``pic_inputs.Box``).
     Returns an opaque context handle (int)."""
     descs = (pic_box_desc * len(boxes))()
@@ -224,12 +224,13 @@ def pic_init(boxes, precision: int, stream=None, kernel: Optional[int] = None, b
         d.cell_base = base
         base += b.ncells
     tun = None
-    if kernel is not None or block or chunk or wg_per_cu or lane_stride:
+    if kernel is not None or block or chunk or wg_per_cu or lane_stride or pad:
         tun = pic_tuning()
         tun.kernel = (PIC_KERNEL_TILED if precision == PIC_FP64 else PIC_KERNEL_BATCHED) \
             if kernel is None else kernel
         tun.block, tun.chunk, tun.wg_per_cu = block, chunk, wg_per_cu
         tun.lane_stride = lane_stride
+        tun.pad = pad
     if stream is None:
         stream = torch.cuda.current_stream().cuda_stream
     h = C.c_void_p()

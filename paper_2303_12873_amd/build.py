@@ -49,6 +49,22 @@ def _compile(unit, extra_flags=()):
     return out
 
 
+MB_OUT = os.path.join(HERE, "libpic_mb.so")
+
+
+def build_microbench(extra_flags=()) -> str:
+    """The hardware-rate microbenchmarks, a library of their own."""
+    os.makedirs(BUILD_DIR, exist_ok=True)
+    obj = _compile(("pic_microbench.hip", "pic_microbench.o", []), extra_flags)
+    tmp = MB_OUT + ".tmp"
+    r = subprocess.run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, obj],
+                       capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
+    os.replace(tmp, MB_OUT)
+    return MB_OUT
+
+
 def build(verbose: bool = False, extra_flags=()) -> str:
     os.makedirs(BUILD_DIR, exist_ok=True)
     jobs = min(len(UNITS), max(1, (os.cpu_count() or 2)))
@@ -60,8 +76,9 @@ def build(verbose: bool = False, extra_flags=()) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
     os.replace(tmp, OUT)
+    build_microbench(extra_flags)
     if verbose:
-        print("built", OUT)
+        print("built", OUT, "and", MB_OUT)
     return OUT
 
 

@@ -49,6 +49,8 @@ struct Slot {
     int *cello = nullptr;
     float *offo[3] = {nullptr, nullptr, nullptr};
     int *carry = nullptr;
+    int *strag = nullptr;       // straggler list of the tiled kernels (np entries)
+    long long strag_cap = 0;
     int *tile_off = nullptr;
     int tile_cap = 0;
     // state of the last binding
@@ -93,6 +95,7 @@ struct pic_ctx {
     int *derr = nullptr;
     size_t lds_field_bytes = 0, lds_bytes = 0;
     int margin = 0;                 // cells staged around each tile
+    int jrow = 0;                   // padded row length of the LDS current tile (0 = none)
     // species
     std::vector<Slot> slots;
     std::vector<DevSpecies> hsp;    // last uploaded table
@@ -115,6 +118,8 @@ struct pic_ctx {
     int *item_counts = nullptr, *item_starts = nullptr;
     int item_slot_cap = 0;
     int *nitems = nullptr, *queue = nullptr;
+    int *strag_count = nullptr;     // per species, capacity dsp_cap
+    int dims = 0;                   // 3 or 2 if every box has it, else 0
     // graphs
     std::map<std::string, hipGraphExec_t> graphs;
     bool capturing = false;
@@ -239,6 +244,13 @@ pic_status bind_species(pic_ctx *c, const pic_species *sp, int nsp, bool need_pu
             sl.sorted = false;
             realloc_happened = true;
         }
+        if (c->tun.kernel != PIC_KERNEL_DIRECT && sl.strag_cap < p.np) {
+            if (c->capturing) return fail(PIC_ERR_STATE, "scratch growth during graph capture");
+            (void)hipStreamSynchronize(c->stream);
+            dfree(sl.strag);
+            if ((st = dalloc(&sl.strag, (size_t)p.np)) != PIC_OK) return st;
+            sl.strag_cap = p.np;
+        }
         DevSpecies &d = t[s];
         std::memset(&d, 0, sizeof(d));
         d.np = p.np;
@@ -257,6 +269,7 @@ pic_status bind_species(pic_ctx *c, const pic_species *sp, int nsp, bool need_pu
         d.w = p.w;
         d.cello = sl.cello;
         d.carry = sl.carry;
+        d.strag = sl.strag;
         d.tile_off = sl.tile_off;
         prefix[s + 1] = prefix[s] + b.ntiles;
     }
@@ -269,9 +282,11 @@ pic_status bind_species(pic_ctx *c, const pic_species *sp, int nsp, bool need_pu
         if (c->dsp_cap < nsp + 1) {
             dfree(c->dsp);
             dfree(c->dprefix);
+            dfree(c->strag_count);
             int cap = nsp + 8;
             if ((st = dalloc(&c->dsp, (size_t)cap)) != PIC_OK) return st;
             if ((st = dalloc(&c->dprefix, (size_t)cap + 1)) != PIC_OK) return st;
+            if ((st = dalloc(&c->strag_count, (size_t)cap)) != PIC_OK) return st;
             c->dsp_cap = cap;
         }
         if (nsp > 0) {
@@ -306,17 +321,20 @@ KParams make_params(pic_ctx *c, const pic_fields *f, int nsp) {
     k.lds_field_bytes = (int)c->lds_field_bytes;
     k.lane_stride = c->tun.lane_stride;
     k.margin = c->margin;
+    k.jrow = c->jrow;
+    k.strag_count = c->strag_count;
     return k;
 }
 
+// form: 0 direct, 1 tiled, 2 batched (persistent), 3 stragglers of 1/2.
 hipError_t launch_particles(pic_ctx *c, const KParams &k, int form, int mode, int grid,
                             int species) {
     const int prec = c->prec == PIC_FP64 ? 0 : 1;
     const int block = c->tun.block;
     switch (c->order) {
-        case 1: return launch_particles_o1(k, prec, form, mode, grid, block, c->lds_bytes, species, c->stream);
-        case 2: return launch_particles_o2(k, prec, form, mode, grid, block, c->lds_bytes, species, c->stream);
-        default: return launch_particles_o3(k, prec, form, mode, grid, block, c->lds_bytes, species, c->stream);
+        case 1: return launch_particles_o1(k, prec, form, mode, c->dims, grid, block, c->lds_bytes, species, c->stream);
+        case 2: return launch_particles_o2(k, prec, form, mode, c->dims, grid, block, c->lds_bytes, species, c->stream);
+        default: return launch_particles_o3(k, prec, form, mode, c->dims, grid, block, c->lds_bytes, species, c->stream);
     }
 }
 
@@ -353,12 +371,17 @@ pic_status run_particles(pic_ctx *c, pic_fields *f, pic_species *sp, int nsp, in
             int grid = (int)((sp[s].np + 255) / 256);
             HIP_TRY(launch_particles(c, k, 0, mode, grid, s));
         }
-    } else if (form == PIC_KERNEL_TILED) {
-        if (c->nslots > 0) HIP_TRY(launch_particles(c, k, 1, mode, c->nslots, 0));
     } else {
-        HIP_TRY(launch_set_int(c->queue, 0, c->stream));
-        int grid = c->cus * c->tun.wg_per_cu;
-        HIP_TRY(launch_particles(c, k, 2, mode, grid, 0));
+        HIP_TRY(launch_zero_ints(c->strag_count, nsp, c->stream));
+        if (form == PIC_KERNEL_TILED) {
+            if (c->nslots > 0) HIP_TRY(launch_particles(c, k, 1, mode, c->nslots, 0));
+        } else {
+            HIP_TRY(launch_set_int(c->queue, 0, c->stream));
+            int grid = c->cus * c->tun.wg_per_cu;
+            HIP_TRY(launch_particles(c, k, 2, mode, grid, 0));
+        }
+        // particles that had left their tile plus margin since the sort
+        HIP_TRY(launch_particles(c, k, 3, mode, c->cus * 2, 0));
     }
     for (int s = 0; s < nsp; ++s) {
         if (mode == MODE_PUSH) c->slots[s].pushed = true;
@@ -540,15 +563,19 @@ pic_status pic_init(pic_ctx **out, const pic_box_desc *boxes, int32_t nboxes, pi
     t.chunk = 4096;
     t.wg_per_cu = 2;
     t.lane_stride = 1;
+    t.pad = 0;
     if (tuning) {
         t.kernel = tuning->kernel;
         if (tuning->block) t.block = tuning->block;
         if (tuning->chunk) t.chunk = tuning->chunk;
         if (tuning->wg_per_cu) t.wg_per_cu = tuning->wg_per_cu;
         if (tuning->lane_stride) t.lane_stride = tuning->lane_stride;
+        t.pad = tuning->pad;
     }
     if (t.kernel < 0 || t.kernel > 2) return fail(PIC_ERR_ARG, "bad kernel form");
-    if (t.block < 64 || t.block > 512 || t.block % 64) return fail(PIC_ERR_ARG, "block must be 64..512, multiple of 64");
+    const int max_block = prec == PIC_FP64 ? 512 : 1024;
+    if (t.block < 64 || t.block > max_block || t.block % 64)
+        return fail(PIC_ERR_ARG, "block must be a multiple of 64 in 64..512 (FP64) or 64..1024 (split)");
     if (t.chunk < 1) return fail(PIC_ERR_ARG, "chunk must be >= 1");
     if (t.wg_per_cu < 1 || t.wg_per_cu > 64) return fail(PIC_ERR_ARG, "wg_per_cu must be 1..64");
     if (t.lane_stride < 1 || t.lane_stride > 64) return fail(PIC_ERR_ARG, "lane_stride must be 1..64");
@@ -608,6 +635,11 @@ pic_status pic_init(pic_ctx **out, const pic_box_desc *boxes, int32_t nboxes, pi
         c->hfp[i + 1] = c->hfp[i] + d.ncells;
     }
     c->total_cells = c->hfp[nboxes];
+    {
+        int n3 = 0;
+        for (int i = 0; i < nboxes; ++i) n3 += boxes[i].dim == 3;
+        c->dims = n3 == nboxes ? 3 : (n3 == 0 ? 2 : 0);
+    }
     // Stage a 1-cell margin around every tile when it fits in LDS.
     if ((fmax1 + 15) / 16 * 16 + jmax1 <= (size_t)LDS_BYTES_MAX) {
         c->margin = 1;
@@ -616,6 +648,33 @@ pic_status pic_init(pic_ctx **out, const pic_box_desc *boxes, int32_t nboxes, pi
     }
     c->lds_field_bytes = (fmax + 15) / 16 * 16;
     c->lds_bytes = c->lds_field_bytes + jmax;
+    // Pad the row of the LDS current tile to the smallest length >= the
+    // tile row that is an odd multiple of the tile width modulo 32 FP64
+    // slots: a wave's lanes spread over a block of tile rows then land on
+    // distinct LDS banks (the FP64 atomic rate halves per 2-way conflict).
+    if (t.pad >= 0) {
+        int tx = 0, need = 0;
+        size_t jpad = 0;
+        for (int i = 0; i < nboxes; ++i) tx = std::max(tx, std::min(boxes[i].tile[0], boxes[i].n[0]));
+        if (tx > 0 && 32 % tx == 0 && tx < 32) {
+            need = tx + halo_jl(o) + halo_jh(o) + 2 * c->margin;
+            int row = need;
+            while (!((row % 32) % tx == 0 && ((row % 32) / tx) % 2 == 1)) ++row;
+            for (int i = 0; i < nboxes; ++i) {
+                const pic_box_desc &b = boxes[i];
+                size_t jr = 3 * 8 * (size_t)row;
+                for (int k = 1; k < 3; ++k) {
+                    if (b.dim == 2 && k == 1) continue;
+                    jr *= (size_t)(std::min(b.tile[k], b.n[k]) + halo_jl(o) + halo_jh(o) + 2 * c->margin);
+                }
+                jpad = std::max(jpad, jr);
+            }
+            if (row <= 2 * need && c->lds_field_bytes + jpad <= (size_t)LDS_BYTES_MAX) {
+                c->jrow = row;
+                c->lds_bytes = c->lds_field_bytes + jpad;
+            }
+        }
+    }
     if (t.kernel != PIC_KERNEL_DIRECT && c->lds_bytes > (size_t)LDS_BYTES_MAX) {
         delete c;
         return fail(PIC_ERR_ARG, "tile too large: LDS need " + std::to_string(c->lds_bytes) + " bytes");
@@ -778,8 +837,10 @@ pic_status pic_free(pic_ctx *c) {
         dfree(sl.cello);
         dfree(sl.carry);
         dfree(sl.tile_off);
+        dfree(sl.strag);
     }
     for (int i = 0; i < 2; ++i) { dfree(c->keys[i]); dfree(c->vals[i]); }
+    dfree(c->strag_count);
     if (c->tmp) (void)hipFree(c->tmp);
     dfree(c->counts);
     dfree(c->scan_scr);

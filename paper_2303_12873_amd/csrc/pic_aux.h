@@ -22,6 +22,7 @@ hipError_t launch_items(const DevSpecies *spt, const int *prefix, int nsp, int n
                         int *counts, int *starts, int *scan_scratch, Item *items, int *nitems,
                         int *queue, hipStream_t st);
 hipError_t launch_set_int(int *p, int v, hipStream_t st);
+hipError_t launch_zero_ints(int *p, int n, hipStream_t st);
 hipError_t launch_zero_j(const DevFields &f, const DevBox *boxes, const long long *fp, int nb,
                          long long total, hipStream_t st);
 hipError_t launch_fdtd(int prec, const DevFields &f, const DevBox *boxes, const long long *fp,
@@ -31,8 +32,9 @@ hipError_t launch_div_edge(const DevBox *boxes, int bi, long long ncells, double
 
 // per-order particle kernels (pic_particles.hip built with PIC_ORDER = 1, 2, 3)
 #define PIC_DECL_ORDER(N)                                                                        \
-    hipError_t launch_particles_o##N(const KParams &prm, int prec, int form, int mode, int grid, \
-                                     int block, size_t lds, int species, hipStream_t st);        \
+    hipError_t launch_particles_o##N(const KParams &prm, int prec, int form, int mode, int dims, \
+                                     int grid, int block, size_t lds, int species,               \
+                                     hipStream_t st);                                            \
     hipError_t particles_lds_limit_o##N(int prec, int bytes);                                    \
     hipError_t launch_rho_o##N(const KParams &prm, int prec, int species, long long np,          \
                                double *rho, hipStream_t st);

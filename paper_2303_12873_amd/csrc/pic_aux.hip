@@ -238,6 +238,11 @@ __global__ void k_item_fill(const DevSpecies *spt, const int *prefix, int nsp, i
 
 __global__ void k_set_int(int *p, int v) { *p = v; }
 
+__global__ void k_zero_ints(int *p, int n) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
 // ------------------------------------------------------------ fields
 
 __device__ inline int box_of(const long long *fp, int nb, long long g) {
@@ -462,6 +467,12 @@ hipError_t launch_items(const DevSpecies *spt, const int *prefix, int nsp, int n
 
 hipError_t launch_set_int(int *p, int v, hipStream_t st) {
     hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, st, p, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_ints(int *p, int n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero_ints, dim3(blocks_for(n, 256)), dim3(256), 0, st, p, n);
     return hipGetLastError();
 }
 

@@ -39,6 +39,7 @@ struct DevSpecies {
     int *cello;
     float *offo[3];
     int *carry;         // split: cell change per axis, 2 bits each (+1)
+    int *strag;         // tiled kernels: particles outside tile + margin
     // exclusive per-tile offsets from the last sort, ntiles+2 entries
     // (the extra bucket holds particles with invalid positions)
     int *tile_off;
@@ -72,6 +73,8 @@ struct KParams {
     int lds_field_bytes;      // offset of the J region in dynamic LDS
     int lane_stride;          // lane -> particle stride inside a work item
     int margin;               // cells staged around each tile (0 or 1)
+    int jrow;                 // minimum row length of the LDS current tile
+    int *strag_count;         // per species: entries in its straggler list
 };
 
 }  // namespace pic

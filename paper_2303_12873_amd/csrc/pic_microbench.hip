@@ -1,0 +1,142 @@
+// Microbenchmarks that measure the hardware rates the PIC kernels are bound
+// by on gfx950: LDS FP32 / FP64 atomic adds and LDS reads under several
+// lane-to-address patterns, global FP64 atomic adds, and HBM copy
+// bandwidth.  Each entry point times its own kernel with HIP events and
+// returns milliseconds (negative on a HIP error).  Used by
+// paper_2303_12873_amd/microbench.py; not part of the PIC step.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace {
+
+constexpr int MB_BLOCK = 512;
+constexpr int MB_LDS_WORDS = 8192;   // 32 KB of 4-byte words
+
+// Lane -> LDS slot.  pattern 0: distinct consecutive slots; 1: groups of 4
+// consecutive lanes share a slot; 2: every lane of the wave the same slot;
+// 3: distinct slots two words apart; 4: distinct slots 15 words apart;
+// 5 / 6: the lanes of a wave on an 8 x 8 block of cells of a tile whose rows
+// are 15 / 24 slots long (the current tile's row without / with padding).
+__device__ inline int slot(int lane, int wave, int pattern) {
+    switch (pattern) {
+        case 0: return wave * 64 + lane;
+        case 1: return wave * 16 + lane / 4;
+        case 2: return wave;
+        case 3: return wave * 128 + 2 * lane;
+        case 4: return (wave * 64 + lane) * 15 % 4096;
+        case 5: return (lane & 7) + 15 * (lane >> 3) + 3 * wave;
+        default: return (lane & 7) + 24 * (lane >> 3) + 3 * wave;
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(MB_BLOCK) k_lds_atomic(int iters, int pattern, T *out) {
+    __shared__ T lds[MB_LDS_WORDS * 4 / sizeof(T)];
+    for (int i = threadIdx.x; i < (int)(MB_LDS_WORDS * 4 / sizeof(T)); i += blockDim.x) lds[i] = T(0);
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int s = slot(lane, wave, pattern) % (MB_LDS_WORDS * 4 / (int)sizeof(T) / 2);
+    const T v = T(1);
+    for (int it = 0; it < iters; ++it) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) unsafeAtomicAdd(&lds[s + u * 8], v);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) out[blockIdx.x] = lds[s];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(MB_BLOCK) k_lds_read(int iters, int pattern, T *out) {
+    __shared__ T lds[MB_LDS_WORDS * 4 / sizeof(T)];
+    for (int i = threadIdx.x; i < (int)(MB_LDS_WORDS * 4 / sizeof(T)); i += blockDim.x) lds[i] = T(i & 7);
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int s = slot(lane, wave, pattern) % (MB_LDS_WORDS * 4 / (int)sizeof(T) / 2);
+    T acc = T(0);
+    for (int it = 0; it < iters; ++it) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc += lds[s + u * 8];
+        s ^= (it & 1);   // keep the loads inside the loop
+    }
+    if (acc == T(-1)) out[blockIdx.x] = acc;
+}
+
+__global__ void k_global_atomic(double *buf, long long nslots, int iters, int collide) {
+    long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    long long s = collide ? (t / 64) % nslots : t % nslots;
+    for (int it = 0; it < iters; ++it) unsafeAtomicAdd(&buf[s], 1.0);
+}
+
+__global__ void k_copy16(const int4 *__restrict__ src, int4 *__restrict__ dst, long long n) {
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    long long stride = (long long)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) dst[i] = src[i];
+}
+
+template <typename F>
+float time_ms(F launch, int reps) {
+    hipEvent_t a, b;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return -1.0f;
+    launch();
+    (void)hipDeviceSynchronize();
+    (void)hipEventRecord(a, 0);
+    for (int r = 0; r < reps; ++r) launch();
+    (void)hipEventRecord(b, 0);
+    (void)hipEventSynchronize(b);
+    float ms = 0.0f;
+    (void)hipEventElapsedTime(&ms, a, b);
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (hipGetLastError() != hipSuccess) return -1.0f;
+    return ms / reps;
+}
+
+}  // namespace
+
+extern "C" {
+
+// LDS atomics (kind 0) or reads (kind 1) of FP32 (bytes 4) or FP64
+// (bytes 8): `blocks` workgroups of 512 threads, each lane issuing 8 * iters
+// operations.  Returns ms per launch.
+float pic_mb_lds(int kind, int bytes, int pattern, int blocks, int iters) {
+    void *out = nullptr;
+    if (hipMalloc(&out, (size_t)blocks * 8) != hipSuccess) return -1.0f;
+    float ms;
+    if (kind == 0 && bytes == 4)
+        ms = time_ms([&] { hipLaunchKernelGGL(k_lds_atomic<float>, dim3(blocks), dim3(MB_BLOCK), 0, 0, iters, pattern, (float *)out); }, 3);
+    else if (kind == 0)
+        ms = time_ms([&] { hipLaunchKernelGGL(k_lds_atomic<double>, dim3(blocks), dim3(MB_BLOCK), 0, 0, iters, pattern, (double *)out); }, 3);
+    else if (bytes == 4)
+        ms = time_ms([&] { hipLaunchKernelGGL(k_lds_read<float>, dim3(blocks), dim3(MB_BLOCK), 0, 0, iters, pattern, (float *)out); }, 3);
+    else
+        ms = time_ms([&] { hipLaunchKernelGGL(k_lds_read<double>, dim3(blocks), dim3(MB_BLOCK), 0, 0, iters, pattern, (double *)out); }, 3);
+    (void)hipFree(out);
+    return ms;
+}
+
+// Global FP64 atomic adds: `threads` threads x `iters` adds onto `nslots`
+// distinct doubles (collide = 0) or one slot per wave (collide = 1).
+float pic_mb_global_atomic(long long threads, long long nslots, int iters, int collide) {
+    double *buf = nullptr;
+    if (hipMalloc(&buf, (size_t)nslots * 8) != hipSuccess) return -1.0f;
+    (void)hipMemset(buf, 0, (size_t)nslots * 8);
+    int blocks = (int)((threads + 255) / 256);
+    float ms = time_ms([&] { hipLaunchKernelGGL(k_global_atomic, dim3(blocks), dim3(256), 0, 0, buf, nslots, iters, collide); }, 3);
+    (void)hipFree(buf);
+    return ms;
+}
+
+// Device-to-device copy of `bytes` (multiple of 16) by a grid-stride kernel.
+float pic_mb_copy(long long bytes, int blocks) {
+    void *a = nullptr, *b = nullptr;
+    if (hipMalloc(&a, (size_t)bytes) != hipSuccess) return -1.0f;
+    if (hipMalloc(&b, (size_t)bytes) != hipSuccess) { (void)hipFree(a); return -1.0f; }
+    (void)hipMemset(a, 1, (size_t)bytes);
+    long long n = bytes / 16;
+    float ms = time_ms([&] { hipLaunchKernelGGL(k_copy16, dim3(blocks), dim3(256), 0, 0, (const int4 *)a, (int4 *)b, n); }, 5);
+    (void)hipFree(a);
+    (void)hipFree(b);
+    return ms;
+}
+
+}  // extern "C"

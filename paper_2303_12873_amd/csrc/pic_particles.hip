@@ -41,6 +41,7 @@ struct F64 {
     using FieldT = double;
     using Acc = double;
     static constexpr int PREC = 0;
+    static constexpr int MAX_BLOCK = 512;    // tiled kernels: threads per workgroup
     // Old position from the species arrays or from scratch.
     __device__ static bool load(const DevBox &b, double *const xs[3], long long i,
                                 int c[3], double f[3]) {
@@ -74,6 +75,7 @@ struct Split {
     using FieldT = float;
     using Acc = double;
     static constexpr int PREC = 1;
+    static constexpr int MAX_BLOCK = 1024;   // 128 VGPRs: 16 waves per CU
     __device__ static bool load(const DevBox &b, const int *cells, float *const offs[3],
                                 long long i, int c[3], float f[3]) {
         int cell = cells[i];
@@ -145,7 +147,7 @@ template <typename A> struct LdsJ {
 // ------------------------------------------------------------ gather
 
 template <int DIM, typename R, class FA>
-__device__ inline R interp(const FA &fa, int comp, const GWin<O, R> &wx,
+__device__ __forceinline__ R interp(const FA &fa, int comp, const GWin<O, R> &wx,
                            const GWin<O, R> &wy, const GWin<O, R> &wz) {
     R sum = R(0);
     if (DIM == 3) {
@@ -178,7 +180,7 @@ __device__ inline R interp(const FA &fa, int comp, const GWin<O, R> &wx,
 // Each component from its own Yee points: E_c is half-shifted along c,
 // B_c along the two other axes.
 template <int DIM, typename R, class FA>
-__device__ inline void gather(const FA &fa, const int c[3], const R f[3], R E[3], R B[3]) {
+__device__ __forceinline__ void gather(const FA &fa, const int c[3], const R f[3], R E[3], R B[3]) {
     GWin<O, R> g0[3], g1[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
@@ -208,12 +210,17 @@ __device__ inline void gather(const FA &fa, const int c[3], const R f[3], R E[3]
 // term: the scaled prefix sums are formed once per axis.  The last edge of
 // each line carries the sum of all dS (zero) and is not written.
 template <int DIM, typename R, class JA>
-__device__ inline void deposit(const JA &ja, const int c0[3], const R f0[3],
+__device__ __forceinline__ void deposit(const JA &ja, const int c0[3], const R f0[3],
                                const int c1[3], const R f1[3], R cq[3], R vy) {
     constexpr int K = O + 2;
     DWin<O, R> wx = deposit_window<O, R>(c0[0], f0[0], c1[0], f1[0]);
     DWin<O, R> wz = deposit_window<O, R>(c0[2], f0[2], c1[2], f1[2]);
     const R third = R(1.0 / 3.0);
+    // Edges written per line: K-1 in general; when the particle stays in its
+    // reference cell along that axis the window's last node carries no
+    // weight, the flux through edge K-2 is sum(dS) = 0, and it is skipped.
+    const int ex = (wx.S0[K - 1] == R(0) && wx.dS[K - 1] == R(0)) ? K - 2 : K - 1;
+    const int ez = (wz.S0[K - 1] == R(0) && wz.dS[K - 1] == R(0)) ? K - 2 : K - 1;
     // The products handed to the FP64 atomics are formed in FP64 from the
     // prefix sums and line weights, so no per-atomic conversion is needed.
     using A = double;
@@ -228,6 +235,7 @@ __device__ inline void deposit(const JA &ja, const int c0[3], const R f0[3],
     }
     if (DIM == 3) {
         DWin<O, R> wy = deposit_window<O, R>(c0[1], f0[1], c1[1], f1[1]);
+        const int ey = (wy.S0[K - 1] == R(0) && wy.dS[K - 1] == R(0)) ? K - 2 : K - 1;
         A py[K - 1];
         {
             R a = R(0);
@@ -242,7 +250,8 @@ __device__ inline void deposit(const JA &ja, const int c0[3], const R f0[3],
                       third * wy.dS[j] * wz.dS[k];
                 if (t == R(0)) continue;
 #pragma unroll
-                for (int i = 0; i < K - 1; ++i) ja.add(0, wx.base + i, wy.base + j, wz.base + k, px[i] * (A)t);
+                for (int i = 0; i < K - 1; ++i)
+                    if (i < ex) ja.add(0, wx.base + i, wy.base + j, wz.base + k, px[i] * (A)t);
             }
         }
 #pragma unroll
@@ -253,7 +262,8 @@ __device__ inline void deposit(const JA &ja, const int c0[3], const R f0[3],
                       third * wz.dS[k] * wx.dS[i];
                 if (t == R(0)) continue;
 #pragma unroll
-                for (int j = 0; j < K - 1; ++j) ja.add(1, wx.base + i, wy.base + j, wz.base + k, py[j] * (A)t);
+                for (int j = 0; j < K - 1; ++j)
+                    if (j < ey) ja.add(1, wx.base + i, wy.base + j, wz.base + k, py[j] * (A)t);
             }
         }
 #pragma unroll
@@ -264,7 +274,8 @@ __device__ inline void deposit(const JA &ja, const int c0[3], const R f0[3],
                       third * wx.dS[i] * wy.dS[j];
                 if (t == R(0)) continue;
 #pragma unroll
-                for (int k = 0; k < K - 1; ++k) ja.add(2, wx.base + i, wy.base + j, wz.base + k, pz[k] * (A)t);
+                for (int k = 0; k < K - 1; ++k)
+                    if (k < ez) ja.add(2, wx.base + i, wy.base + j, wz.base + k, pz[k] * (A)t);
             }
         }
     } else {
@@ -273,14 +284,16 @@ __device__ inline void deposit(const JA &ja, const int c0[3], const R f0[3],
             R t = wz.S0[k] + R(0.5) * wz.dS[k];
             if (t == R(0)) continue;
 #pragma unroll
-            for (int i = 0; i < K - 1; ++i) ja.add(0, wx.base + i, 0, wz.base + k, px[i] * (A)t);
+            for (int i = 0; i < K - 1; ++i)
+                if (i < ex) ja.add(0, wx.base + i, 0, wz.base + k, px[i] * (A)t);
         }
 #pragma unroll
         for (int i = 0; i < K; ++i) {
             R t = wx.S0[i] + R(0.5) * wx.dS[i];
             if (t == R(0)) continue;
 #pragma unroll
-            for (int k = 0; k < K - 1; ++k) ja.add(2, wx.base + i, 0, wz.base + k, pz[k] * (A)t);
+            for (int k = 0; k < K - 1; ++k)
+                if (k < ez) ja.add(2, wx.base + i, 0, wz.base + k, pz[k] * (A)t);
         }
         const A cy = (A)(cq[1] * vy);
 #pragma unroll
@@ -311,10 +324,14 @@ struct Tile {
     }
 };
 
-template <int DIM, class P, int MODE, class FL, class JL>
-__device__ inline void particle(const DevBox &b, const DevSpecies &sp, long long i,
-                                const DevFields &gf, const Tile *tile, const FL *lf,
-                                const JL *lj, int *err) {
+// One particle update.  TILED: gather and deposit through the work item's
+// LDS tiles; a particle whose cell lies outside the tile plus margin is not
+// updated here but appended to its species' straggler list (processed by
+// k_strag right after).  Not TILED: global arrays with wrapped indices.
+template <int DIM, class P, int MODE, bool TILED, class FL, class JL>
+__device__ __forceinline__ void particle(const DevBox &b, const DevSpecies &sp, long long i,
+                                         const DevFields &gf, const Tile *tile, const FL *lf,
+                                         const JL *lj, int *err, int *strag_count) {
     using R = typename P::R;
     using FT = typename P::FieldT;
     int c0[3], c1[3];
@@ -329,13 +346,18 @@ __device__ inline void particle(const DevBox &b, const DevSpecies &sp, long long
         else ok = P::load(b, sp.cello, sp.offo, i, c0, f0);
     }
     if (!ok) { flag_range(err); return; }
-    const bool local = tile != nullptr && tile->holds(c0);
+    if constexpr (TILED) {
+        if (!tile->holds(c0)) {
+            sp.strag[atomicAdd(strag_count, 1)] = (int)i;
+            return;
+        }
+    }
     const R *ua[3] = {(const R *)sp.u[0], (const R *)sp.u[1], (const R *)sp.u[2]};
     u[0] = ua[0][i]; u[1] = ua[1][i]; u[2] = ua[2][i];
     const R dt = (R)b.dt;
     if (MODE & MODE_PUSH) {
         R E[3], B[3];
-        if (local) {
+        if constexpr (TILED) {
             gather<DIM, R>(*lf, c0, f0, E, B);
         } else {
             GlobalField<FT> g;
@@ -465,9 +487,7 @@ __device__ inline void particle(const DevBox &b, const DevSpecies &sp, long long
             cq[1] = (R)(sp.q / dV) * wgt;
             vy = u[1] * gi;
         }
-        bool jlocal = local;
-        if (MODE == MODE_DEPOSIT && tile != nullptr) jlocal = tile->holds(c0);
-        if (jlocal) {
+        if constexpr (TILED) {
             deposit<DIM, R>(*lj, c0, f0, c1, f1, cq, vy);
         } else {
             GlobalJ g;
@@ -517,9 +537,30 @@ __global__ void __launch_bounds__(256) k_direct(KParams prm, int s) {
     using FL = LdsField<typename P::FieldT>;
     using JL = LdsJ<typename P::Acc>;
     if (b.dim == 3)
-        particle<3, P, MODE, FL, JL>(b, sp, i, prm.f, nullptr, nullptr, nullptr, prm.err);
+        particle<3, P, MODE, false, FL, JL>(b, sp, i, prm.f, nullptr, nullptr, nullptr, prm.err, nullptr);
     else
-        particle<2, P, MODE, FL, JL>(b, sp, i, prm.f, nullptr, nullptr, nullptr, prm.err);
+        particle<2, P, MODE, false, FL, JL>(b, sp, i, prm.f, nullptr, nullptr, nullptr, prm.err, nullptr);
+}
+
+// Particles the tiled kernels found outside their tile plus margin: the
+// global-memory update, over every species' straggler list.
+template <class P, int MODE>
+__global__ void __launch_bounds__(256) k_strag(KParams prm) {
+    using FL = LdsField<typename P::FieldT>;
+    using JL = LdsJ<typename P::Acc>;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (int s = 0; s < prm.nsp; ++s) {
+        const DevSpecies &sp = prm.species[s];
+        const DevBox &b = prm.boxes[sp.box];
+        const long long n = prm.strag_count[s];
+        for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride) {
+            const long long i = sp.strag[k];
+            if (b.dim == 3)
+                particle<3, P, MODE, false, FL, JL>(b, sp, i, prm.f, nullptr, nullptr, nullptr, prm.err, nullptr);
+            else
+                particle<2, P, MODE, false, FL, JL>(b, sp, i, prm.f, nullptr, nullptr, nullptr, prm.err, nullptr);
+        }
+    }
 }
 
 // ------------------------------------------------------------ tiled / batched
@@ -550,7 +591,7 @@ struct RegionWalk {
 };
 
 template <int DIM, class P, int MODE>
-__device__ void process_item(const KParams &prm, const Item &it, char *smem) {
+__device__ __forceinline__ void process_item(const KParams &prm, const Item &it, char *smem) {
     using FT = typename P::FieldT;
     using A = typename P::Acc;
     const DevSpecies &sp = prm.species[it.s];
@@ -584,7 +625,9 @@ __device__ void process_item(const KParams &prm, const Item &it, char *smem) {
     // current region: nodes [t0 - JL, t0 + te + JH) per active axis
     lj.base = (A *)(smem + prm.lds_field_bytes);
     const int JL = H::JL + tile.mg, JW = H::JL + H::JH + 2 * tile.mg;
-    lj.o0 = tile.t0[0] - JL; lj.M0 = tile.te[0] + JW;
+    // Row length of the LDS current tile: padded (prm.jrow, from the host)
+    // so that a wave's lanes on an 8-wide block of rows hit distinct banks.
+    lj.o0 = tile.t0[0] - JL; lj.M0 = max(tile.te[0] + JW, prm.jrow);
     lj.o2 = tile.t0[2] - JL;
     int M2 = tile.te[2] + JW;
     if (DIM == 3) { lj.o1 = tile.t0[1] - JL; lj.M1 = tile.te[1] + JW; }
@@ -624,7 +667,8 @@ __device__ void process_item(const KParams &prm, const Item &it, char *smem) {
         for (int sl = tid; sl < total; sl += bs) {
             const int idx = r * S + q;
             if (idx < n)
-                particle<DIM, P, MODE>(b, sp, (long long)(it.p0 + idx), prm.f, &tile, &lf, &lj, prm.err);
+                particle<DIM, P, MODE, true>(b, sp, (long long)(it.p0 + idx), prm.f, &tile, &lf, &lj,
+                                             prm.err, prm.strag_count + it.s);
             r += dr;
             q += dq;
             if (r >= G) { r -= G; q += 1; }
@@ -647,8 +691,10 @@ __device__ void process_item(const KParams &prm, const Item &it, char *smem) {
     __syncthreads();
 }
 
-template <class P, int MODE, bool PERSISTENT>
-__global__ void __launch_bounds__(512) k_tiled(KParams prm) {
+// DIMS: 3 or 2 when every box of the context has that dimensionality (one
+// code path, fewer registers), 0 for a mix.
+template <class P, int MODE, bool PERSISTENT, int DIMS>
+__global__ void __launch_bounds__(P::MAX_BLOCK) k_tiled(KParams prm) {
     extern __shared__ __attribute__((aligned(16))) char smem[];
     __shared__ Item cur;
     for (int round = 0;; ++round) {
@@ -672,46 +718,75 @@ __global__ void __launch_bounds__(512) k_tiled(KParams prm) {
             it = Item{s, t, off[t], off[t + 1]};
         }
         if (it.p1 <= it.p0) continue;
-        const DevBox &b = prm.boxes[prm.species[it.s].box];
-        if (b.dim == 3) process_item<3, P, MODE>(prm, it, smem);
-        else process_item<2, P, MODE>(prm, it, smem);
+        if constexpr (DIMS == 3) {
+            process_item<3, P, MODE>(prm, it, smem);
+        } else if constexpr (DIMS == 2) {
+            process_item<2, P, MODE>(prm, it, smem);
+        } else {
+            const DevBox &b = prm.boxes[prm.species[it.s].box];
+            if (b.dim == 3) process_item<3, P, MODE>(prm, it, smem);
+            else process_item<2, P, MODE>(prm, it, smem);
+        }
     }
 }
 
-template <class P, int MODE>
-hipError_t launch_mode(const KParams &prm, int form, int grid, int block, size_t lds,
-                       int species, hipStream_t st) {
-    if (form == 0) {
-        hipLaunchKernelGGL((k_direct<P, MODE>), dim3(grid), dim3(256), 0, st, prm, species);
-    } else if (form == 1) {
-        hipLaunchKernelGGL((k_tiled<P, MODE, false>), dim3(grid), dim3(block), lds, st, prm);
-    } else {
-        hipLaunchKernelGGL((k_tiled<P, MODE, true>), dim3(grid), dim3(block), lds, st, prm);
+template <class P, int MODE, bool PERS>
+hipError_t launch_tiled_dims(const KParams &prm, int dims, int grid, int block, size_t lds,
+                             hipStream_t st) {
+    if constexpr (MODE == MODE_FUSED) {
+        if (dims == 3) {
+            hipLaunchKernelGGL((k_tiled<P, MODE, PERS, 3>), dim3(grid), dim3(block), lds, st, prm);
+            return hipGetLastError();
+        }
+        if (dims == 2) {
+            hipLaunchKernelGGL((k_tiled<P, MODE, PERS, 2>), dim3(grid), dim3(block), lds, st, prm);
+            return hipGetLastError();
+        }
     }
+    hipLaunchKernelGGL((k_tiled<P, MODE, PERS, 0>), dim3(grid), dim3(block), lds, st, prm);
     return hipGetLastError();
 }
 
+template <class P, int MODE>
+hipError_t launch_mode(const KParams &prm, int form, int dims, int grid, int block, size_t lds,
+                       int species, hipStream_t st) {
+    if (form == 0) {
+        hipLaunchKernelGGL((k_direct<P, MODE>), dim3(grid), dim3(256), 0, st, prm, species);
+        return hipGetLastError();
+    }
+    if (form == 3) {
+        hipLaunchKernelGGL((k_strag<P, MODE>), dim3(grid), dim3(256), 0, st, prm);
+        return hipGetLastError();
+    }
+    if (form == 1) return launch_tiled_dims<P, MODE, false>(prm, dims, grid, block, lds, st);
+    return launch_tiled_dims<P, MODE, true>(prm, dims, grid, block, lds, st);
+}
+
 template <class P>
-hipError_t launch_prec(const KParams &prm, int form, int mode, int grid, int block,
+hipError_t launch_prec(const KParams &prm, int form, int mode, int dims, int grid, int block,
                        size_t lds, int species, hipStream_t st) {
-    if (mode == MODE_PUSH) return launch_mode<P, MODE_PUSH>(prm, form, grid, block, lds, species, st);
-    if (mode == MODE_DEPOSIT) return launch_mode<P, MODE_DEPOSIT>(prm, form, grid, block, lds, species, st);
-    return launch_mode<P, MODE_FUSED>(prm, form, grid, block, lds, species, st);
+    if (mode == MODE_PUSH) return launch_mode<P, MODE_PUSH>(prm, form, dims, grid, block, lds, species, st);
+    if (mode == MODE_DEPOSIT) return launch_mode<P, MODE_DEPOSIT>(prm, form, dims, grid, block, lds, species, st);
+    return launch_mode<P, MODE_FUSED>(prm, form, dims, grid, block, lds, species, st);
+}
+
+template <class P, int MODE, bool PERS, int DIMS>
+hipError_t set_lds(int bytes) {
+    return hipFuncSetAttribute((const void *)&k_tiled<P, MODE, PERS, DIMS>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
 template <class P>
 hipError_t lds_limit_prec(int bytes) {
     hipError_t e = hipSuccess;
-#define PIC_SET(M)                                                                                  \
-    if (e == hipSuccess)                                                                            \
-        e = hipFuncSetAttribute((const void *)&k_tiled<P, M, false>,                              \
-                                hipFuncAttributeMaxDynamicSharedMemorySize, bytes);                 \
-    if (e == hipSuccess)                                                                            \
-        e = hipFuncSetAttribute((const void *)&k_tiled<P, M, true>,                               \
-                                hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-    PIC_SET(MODE_PUSH)
-    PIC_SET(MODE_DEPOSIT)
-    PIC_SET(MODE_FUSED)
+#define PIC_SET(M, D)                                               \
+    if (e == hipSuccess) e = set_lds<P, M, false, D>(bytes);        \
+    if (e == hipSuccess) e = set_lds<P, M, true, D>(bytes);
+    PIC_SET(MODE_PUSH, 0)
+    PIC_SET(MODE_DEPOSIT, 0)
+    PIC_SET(MODE_FUSED, 0)
+    PIC_SET(MODE_FUSED, 2)
+    PIC_SET(MODE_FUSED, 3)
 #undef PIC_SET
     return e;
 }
@@ -765,10 +840,10 @@ __global__ void k_rho(KParams prm, int s, double *rho) {
 #define PIC_CAT(a, b) PIC_CAT2(a, b)
 
 hipError_t PIC_CAT(launch_particles_o, PIC_ORDER)(const KParams &prm, int prec, int form, int mode,
-                                                 int grid, int block, size_t lds, int species,
-                                                 hipStream_t st) {
-    if (prec == 0) return launch_prec<F64>(prm, form, mode, grid, block, lds, species, st);
-    return launch_prec<Split>(prm, form, mode, grid, block, lds, species, st);
+                                                 int dims, int grid, int block, size_t lds,
+                                                 int species, hipStream_t st) {
+    if (prec == 0) return launch_prec<F64>(prm, form, mode, dims, grid, block, lds, species, st);
+    return launch_prec<Split>(prm, form, mode, dims, grid, block, lds, species, st);
 }
 
 hipError_t PIC_CAT(particles_lds_limit_o, PIC_ORDER)(int prec, int bytes) {
