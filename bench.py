@@ -171,7 +171,8 @@ def main():
     ap.add_argument("--tile64", type=int, nargs=3, default=(8, 8, 4))
     ap.add_argument("--block", type=int, default=1024)
     ap.add_argument("--block64", type=int, default=512)
-    ap.add_argument("--stride", type=int, default=4, help="lane stride (particles per cell per species)")
+    ap.add_argument("--stride", type=int, default=1, help="FP32 lane stride (1: quad-pooled deposit)")
+    ap.add_argument("--stride64", type=int, default=4, help="FP64 lane stride")
     ap.add_argument("--chunk", type=int, default=4096)
     ap.add_argument("--wg-per-cu", type=int, default=2)
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison form")
@@ -205,7 +206,7 @@ def main():
     if not args.no_fp64:
         log("FP64 plain (tiled) form")
         r64 = run_form(wl, pic.PIC_FP64, pic.PIC_KERNEL_TILED, max(3, args.steps // 4), 1,
-                       args.sort_every, args.tile64, args.block64, 0, 0, args.stride)
+                       args.sort_every, args.tile64, args.block64, 0, 0, args.stride64)
         log(f"  {r64}")
 
     value = r32["np"] * 1e3 / r32["ms_step"]

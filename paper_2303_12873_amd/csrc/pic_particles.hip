@@ -18,6 +18,8 @@
 // Precision policies: F64 (FP64 positions, momenta, fields, LDS J) and
 // Split (int32 cell + FP32 in-cell offset, FP32 momenta, fields, gather,
 // push; current accumulated in an FP64 LDS tile, flushed to FP64 J).
+#include <type_traits>
+
 #include "pic_dev.h"
 #include "pic_math.h"
 #include "pic_aux.h"
@@ -99,6 +101,7 @@ struct Split {
 // ------------------------------------------------------------ accessors
 
 template <typename T> struct GlobalField {
+    static constexpr bool LDS = false;
     const T *F[6];
     int n0, n1, n2;
     bool any;
@@ -113,14 +116,21 @@ template <typename T> struct GlobalField {
 };
 
 template <typename T> struct LdsField {
+    static constexpr bool LDS = true;
     const T *base;
     int o0, o1, o2, L0, L1, L012;
     __device__ inline T load(int comp, int i, int j, int k) const {
         return base[comp * L012 + (i - o0) + L0 * ((j - o1) + L1 * (k - o2))];
     }
+    // Address of node (i, j, k) of a component; neighbours are reached by
+    // adding the uniform row (L0) and plane (L0 L1) strides.
+    __device__ inline const T *at(int comp, int i, int j, int k) const {
+        return base + comp * L012 + (i - o0) + L0 * ((j - o1) + L1 * (k - o2));
+    }
 };
 
 struct GlobalJ {
+    static constexpr bool LDS = false;
     double *J[3];
     int n0, n1, n2;
     bool any;
@@ -136,8 +146,12 @@ struct GlobalJ {
 };
 
 template <typename A> struct LdsJ {
+    static constexpr bool LDS = true;
     A *base;
     int o0, o1, o2, M0, M1, M012;
+    __device__ inline A *at(int comp, int i, int j, int k) const {
+        return base + comp * M012 + (i - o0) + M0 * ((j - o1) + M1 * (k - o2));
+    }
     template <typename V>
     __device__ inline void add(int comp, int i, int j, int k, V v) const {
         unsafeAtomicAdd(&base[comp * M012 + (i - o0) + M0 * ((j - o1) + M1 * (k - o2))], (A)v);
@@ -150,6 +164,35 @@ template <int DIM, typename R, class FA>
 __device__ __forceinline__ R interp(const FA &fa, int comp, const GWin<O, R> &wx,
                            const GWin<O, R> &wy, const GWin<O, R> &wz) {
     R sum = R(0);
+    if constexpr (FA::LDS) {
+        const auto *p0 = fa.at(comp, wx.base, wy.base, wz.base);
+        const int rs = fa.L0, ps = fa.L0 * fa.L1;
+        if (DIM == 3) {
+#pragma unroll
+            for (int kk = 0; kk <= O; ++kk) {
+                R sy = R(0);
+#pragma unroll
+                for (int jj = 0; jj <= O; ++jj) {
+                    const auto *r = p0 + kk * ps + jj * rs;
+                    R sx = R(0);
+#pragma unroll
+                    for (int ii = 0; ii <= O; ++ii) sx += wx.w[ii] * (R)r[ii];
+                    sy += wy.w[jj] * sx;
+                }
+                sum += wz.w[kk] * sy;
+            }
+        } else {
+#pragma unroll
+            for (int kk = 0; kk <= O; ++kk) {
+                const auto *r = p0 + kk * ps;
+                R sx = R(0);
+#pragma unroll
+                for (int ii = 0; ii <= O; ++ii) sx += wx.w[ii] * (R)r[ii];
+                sum += wz.w[kk] * sx;
+            }
+        }
+        return sum;
+    }
     if (DIM == 3) {
 #pragma unroll
         for (int kk = 0; kk <= O; ++kk) {
@@ -242,6 +285,53 @@ __device__ __forceinline__ void deposit(const JA &ja, const int c0[3], const R f
 #pragma unroll
             for (int i = 0; i < K - 1; ++i) { a += wy.dS[i]; py[i] = (A)(cq[1] * a); }
         }
+        if constexpr (JA::LDS) {
+            // one base address per component; lines by uniform strides
+            const int rs = ja.M0, ps = ja.M0 * ja.M1;
+            A *q0 = ja.at(0, wx.base, wy.base, wz.base);
+            A *q1 = ja.at(1, wx.base, wy.base, wz.base);
+            A *q2 = ja.at(2, wx.base, wy.base, wz.base);
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+#pragma unroll
+                for (int j = 0; j < K; ++j) {
+                    R t = wy.S0[j] * wz.S0[k] + R(0.5) * (wy.dS[j] * wz.S0[k] + wy.S0[j] * wz.dS[k]) +
+                          third * wy.dS[j] * wz.dS[k];
+                    if (t == R(0)) continue;
+                    A *line = q0 + k * ps + j * rs;
+#pragma unroll
+                    for (int i = 0; i < K - 1; ++i)
+                        if (i < ex) unsafeAtomicAdd(line + i, px[i] * (A)t);
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+#pragma unroll
+                for (int i = 0; i < K; ++i) {
+                    R t = wz.S0[k] * wx.S0[i] + R(0.5) * (wz.dS[k] * wx.S0[i] + wz.S0[k] * wx.dS[i]) +
+                          third * wz.dS[k] * wx.dS[i];
+                    if (t == R(0)) continue;
+                    A *line = q1 + k * ps + i;
+#pragma unroll
+                    for (int j = 0; j < K - 1; ++j)
+                        if (j < ey) unsafeAtomicAdd(line + j * rs, py[j] * (A)t);
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < K; ++j) {
+#pragma unroll
+                for (int i = 0; i < K; ++i) {
+                    R t = wx.S0[i] * wy.S0[j] + R(0.5) * (wx.dS[i] * wy.S0[j] + wx.S0[i] * wy.dS[j]) +
+                          third * wx.dS[i] * wy.dS[j];
+                    if (t == R(0)) continue;
+                    A *line = q2 + j * rs + i;
+#pragma unroll
+                    for (int k = 0; k < K - 1; ++k)
+                        if (k < ez) unsafeAtomicAdd(line + k * ps, pz[k] * (A)t);
+                }
+            }
+            return;
+        }
 #pragma unroll
         for (int k = 0; k < K; ++k) {
 #pragma unroll
@@ -279,6 +369,39 @@ __device__ __forceinline__ void deposit(const JA &ja, const int c0[3], const R f
             }
         }
     } else {
+        if constexpr (JA::LDS) {
+            const int ps = ja.M0 * ja.M1;
+            A *q0 = ja.at(0, wx.base, 0, wz.base);
+            A *q1 = ja.at(1, wx.base, 0, wz.base);
+            A *q2 = ja.at(2, wx.base, 0, wz.base);
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                R t = wz.S0[k] + R(0.5) * wz.dS[k];
+                if (t == R(0)) continue;
+#pragma unroll
+                for (int i = 0; i < K - 1; ++i)
+                    if (i < ex) unsafeAtomicAdd(q0 + k * ps + i, px[i] * (A)t);
+            }
+#pragma unroll
+            for (int i = 0; i < K; ++i) {
+                R t = wx.S0[i] + R(0.5) * wx.dS[i];
+                if (t == R(0)) continue;
+#pragma unroll
+                for (int k = 0; k < K - 1; ++k)
+                    if (k < ez) unsafeAtomicAdd(q2 + k * ps + i, pz[k] * (A)t);
+            }
+            const A cy = (A)(cq[1] * vy);
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+#pragma unroll
+                for (int i = 0; i < K; ++i) {
+                    R a = wx.S0[i] * wz.S0[k] + R(0.5) * (wx.dS[i] * wz.S0[k] + wx.S0[i] * wz.dS[k]) +
+                          third * wx.dS[i] * wz.dS[k];
+                    if (a != R(0)) unsafeAtomicAdd(q1 + k * ps + i, cy * (A)a);
+                }
+            }
+            return;
+        }
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             R t = wz.S0[k] + R(0.5) * wz.dS[k];
@@ -526,6 +649,296 @@ __device__ __forceinline__ void particle(const DevBox &b, const DevSpecies &sp, 
     }
 }
 
+// ------------------------------------------------------------ converged fused path
+//
+// The fused tiled kernels run every lane of a wave through the whole update
+// (lanes without a particle carry weight 0), so that the four lanes of a
+// quad can pool their deposit values with DPP before one of them issues the
+// LDS atomic: with the particles of a cell in consecutive lanes (lane stride
+// 1, ppc a multiple of 4) a quad shares one stencil, and the LDS sees a
+// quarter of the atomic lanes.
+
+template <int CTRL> __device__ inline int dpp_i(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, true);
+}
+template <int CTRL> __device__ inline float dpp(float v) {
+    return __int_as_float(dpp_i<CTRL>(__float_as_int(v)));
+}
+template <int CTRL> __device__ inline double dpp(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = dpp_i<CTRL>((int)(b & 0xffffffffll));
+    const int hi = dpp_i<CTRL>((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+// quad_perm selectors: [1,0,3,2], [2,3,0,1], [0,0,0,0]
+constexpr int QP_SWAP1 = 0xB1, QP_SWAP2 = 0x4E, QP_LANE0 = 0x00;
+
+template <typename T> __device__ inline T quad_sum(T v) {
+    v += dpp<QP_SWAP1>(v);
+    v += dpp<QP_SWAP2>(v);
+    return v;
+}
+
+// Reduce-scatter over a quad: lane r (r = lane mod 4) returns the sum over
+// the quad's lanes of their v[r].  Two exchange steps: lanes r and r^2 swap
+// the half of the values the other keeps, then lanes r and r^1 do the same.
+template <typename T> __device__ inline T quad_reduce_scatter(const T v[4]) {
+    const int r = threadIdx.x & 3;
+    const bool b1 = (r & 2) != 0, b0 = (r & 1) != 0;
+    const T sendA = b1 ? v[0] : v[2], sendB = b1 ? v[1] : v[3];
+    const T keepA = b1 ? v[2] : v[0], keepB = b1 ? v[3] : v[1];
+    const T a0 = keepA + dpp<QP_SWAP2>(sendA);
+    const T a1 = keepB + dpp<QP_SWAP2>(sendB);
+    const T send = b0 ? a0 : a1;
+    return (b0 ? a1 : a0) + dpp<QP_SWAP1>(send);
+}
+
+__device__ inline bool wave_any(bool p) { return __ballot(p) != 0ull; }
+
+// Esirkepov deposit into the LDS current tile with every lane active.
+// QUAD: lanes whose quad shares one window pool values and the quad's
+// first lane adds the sum; other lanes add their own non-zero values.
+template <int DIM, bool QUAD, typename R, class JA>
+__device__ __forceinline__ void deposit_converged(const JA &ja, const int c0[3], const R f0[3],
+                                                  const int c1[3], const R f1[3], const R cq[3],
+                                                  R vy, bool valid) {
+    using A = typename std::remove_pointer<decltype(ja.base)>::type;
+    constexpr int K = O + 2;
+    DWin<O, R> wx = deposit_window<O, R>(c0[0], f0[0], c1[0], f1[0]);
+    DWin<O, R> wz = deposit_window<O, R>(c0[2], f0[2], c1[2], f1[2]);
+    DWin<O, R> wy;
+    if (DIM == 3) wy = deposit_window<O, R>(c0[1], f0[1], c1[1], f1[1]);
+    const R third = R(1.0 / 3.0);
+    const bool lastx = !(wx.S0[K - 1] == R(0) && wx.dS[K - 1] == R(0));
+    const bool lastz = !(wz.S0[K - 1] == R(0) && wz.dS[K - 1] == R(0));
+    const bool lasty = DIM == 3 && !(wy.S0[K - 1] == R(0) && wy.dS[K - 1] == R(0));
+    const int exu = wave_any(lastx) ? K - 1 : K - 2;
+    const int ezu = wave_any(lastz) ? K - 1 : K - 2;
+    const int eyu = wave_any(lasty) ? K - 1 : K - 2;
+    R px[K - 1], py[K - 1], pz[K - 1];
+    {
+        R a = R(0), b = R(0), c = R(0);
+#pragma unroll
+        for (int i = 0; i < K - 1; ++i) {
+            a += wx.dS[i]; px[i] = (i < K - 2 || lastx) ? cq[0] * a : R(0);
+            c += wz.dS[i]; pz[i] = (i < K - 2 || lastz) ? cq[2] * c : R(0);
+            if (DIM == 3) { b += wy.dS[i]; py[i] = (i < K - 2 || lasty) ? cq[1] * b : R(0); }
+        }
+    }
+    bool pool = false;
+    if constexpr (QUAD) {
+        const int by = DIM == 3 ? wy.base : 0;
+        bool same = valid && wx.base == dpp_i<QP_LANE0>(wx.base) && by == dpp_i<QP_LANE0>(by) &&
+                    wz.base == dpp_i<QP_LANE0>(wz.base);
+        int f = same ? 1 : 0;
+        f &= dpp_i<QP_SWAP1>(f);
+        f &= dpp_i<QP_SWAP2>(f);
+        pool = f != 0;
+    }
+    const bool lead = (threadIdx.x & 3) == 0;
+    // One line of up to 4 edges, `ne` of them written (wave-uniform), at
+    // addresses base + e * stride.  Pooled quads: lane r adds edge r.
+    auto line_put = [&](A *base, int stride, const R *pv, R t, int ne) {
+        R v[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v[e] = (e < K - 1 && e < ne) ? pv[e] * t : R(0);
+        if constexpr (QUAD) {
+            const R sc = quad_reduce_scatter(v);
+            const int r = threadIdx.x & 3;
+            if (pool) {
+                if (r < ne && sc != R(0)) unsafeAtomicAdd(base + r * stride, (A)sc);
+            } else {
+#pragma unroll
+                for (int e = 0; e < K - 1; ++e)
+                    if (e < ne && v[e] != R(0)) unsafeAtomicAdd(base + e * stride, (A)v[e]);
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < K - 1; ++e)
+                if (e < ne && v[e] != R(0)) unsafeAtomicAdd(base + e * stride, (A)v[e]);
+        }
+    };
+    auto put = [&](A *addr, R v) {
+        if constexpr (QUAD) {
+            const R s = quad_sum(v);
+            if (pool) {
+                if (lead) unsafeAtomicAdd(addr, (A)s);
+            } else if (v != R(0)) {
+                unsafeAtomicAdd(addr, (A)v);
+            }
+        } else {
+            if (v != R(0)) unsafeAtomicAdd(addr, (A)v);
+        }
+    };
+    const int rs = ja.M0, ps = ja.M0 * ja.M1;
+    if (DIM == 3) {
+        A *q0 = ja.at(0, wx.base, wy.base, wz.base);
+        A *q1 = ja.at(1, wx.base, wy.base, wz.base);
+        A *q2 = ja.at(2, wx.base, wy.base, wz.base);
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+#pragma unroll
+            for (int j = 0; j < K; ++j) {
+                R t = wy.S0[j] * wz.S0[k] + R(0.5) * (wy.dS[j] * wz.S0[k] + wy.S0[j] * wz.dS[k]) +
+                      third * wy.dS[j] * wz.dS[k];
+                if (!wave_any(t != R(0))) continue;
+                line_put(q0 + k * ps + j * rs, 1, px, t, exu);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+#pragma unroll
+            for (int i = 0; i < K; ++i) {
+                R t = wz.S0[k] * wx.S0[i] + R(0.5) * (wz.dS[k] * wx.S0[i] + wz.S0[k] * wx.dS[i]) +
+                      third * wz.dS[k] * wx.dS[i];
+                if (!wave_any(t != R(0))) continue;
+                line_put(q1 + k * ps + i, rs, py, t, eyu);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+#pragma unroll
+            for (int i = 0; i < K; ++i) {
+                R t = wx.S0[i] * wy.S0[j] + R(0.5) * (wx.dS[i] * wy.S0[j] + wx.S0[i] * wy.dS[j]) +
+                      third * wx.dS[i] * wy.dS[j];
+                if (!wave_any(t != R(0))) continue;
+                line_put(q2 + j * rs + i, ps, pz, t, ezu);
+            }
+        }
+    } else {
+        A *q0 = ja.at(0, wx.base, 0, wz.base);
+        A *q1 = ja.at(1, wx.base, 0, wz.base);
+        A *q2 = ja.at(2, wx.base, 0, wz.base);
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            R t = wz.S0[k] + R(0.5) * wz.dS[k];
+            if (!wave_any(t != R(0))) continue;
+            line_put(q0 + k * ps, 1, px, t, exu);
+        }
+#pragma unroll
+        for (int i = 0; i < K; ++i) {
+            R t = wx.S0[i] + R(0.5) * wx.dS[i];
+            if (!wave_any(t != R(0))) continue;
+            line_put(q2 + i, ps, pz, t, ezu);
+        }
+        const R cy = cq[1] * vy;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+#pragma unroll
+            for (int i = 0; i < K; ++i) {
+                R a = wx.S0[i] * wz.S0[k] + R(0.5) * (wx.dS[i] * wz.S0[k] + wx.S0[i] * wz.dS[k]) +
+                      third * wx.dS[i] * wz.dS[k];
+                if (!wave_any(a != R(0))) continue;
+                put(q1 + k * ps + i, cy * a);
+            }
+        }
+    }
+}
+
+// Fused gather / push / advance / deposit / wrap of one slot of a tiled work
+// item, with every lane active.  `have` is false for slots past the item's
+// end; such lanes, particles with invalid input and particles outside the
+// tile plus margin (queued as stragglers) compute on a dummy position at the
+// tile origin with weight 0 and store nothing.
+template <int DIM, class P, bool QUAD, class FL, class JL>
+__device__ __forceinline__ void particle_converged(const DevBox &b, const DevSpecies &sp,
+                                                   long long i, bool have, const Tile &tile,
+                                                   const FL &lf, const JL &lj, int *err,
+                                                   int *strag_count) {
+    using R = typename P::R;
+    int c0[3], c1[3];
+    R f0[3], f1[3], u[3] = {R(0), R(0), R(0)};
+    bool valid = have;
+    if (valid) {
+        bool ok;
+        if constexpr (P::PREC == 0) ok = P::load(b, sp.x, i, c0, f0);
+        else ok = P::load(b, sp.cell, sp.off, i, c0, f0);
+        if (!ok) { flag_range(err); valid = false; }
+    }
+    if (valid && !tile.holds(c0)) {
+        sp.strag[atomicAdd(strag_count, 1)] = (int)i;
+        valid = false;
+    }
+    if (!valid) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) { c0[d] = tile.t0[d]; f0[d] = R(0); }
+    } else {
+        const R *ua[3] = {(const R *)sp.u[0], (const R *)sp.u[1], (const R *)sp.u[2]};
+        u[0] = ua[0][i]; u[1] = ua[1][i]; u[2] = ua[2][i];
+    }
+    R E[3], B[3];
+    gather<DIM, R>(lf, c0, f0, E, B);
+    const R dt = (R)b.dt;
+    const R h = (R)(sp.q * b.dt / (2.0 * sp.m));
+    boris<R>(h, E, B, u);
+    const R gi = R(1) / sqrt(R(1) + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+    R disp[3];
+    bool good = true;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        disp[d] = (DIM == 2 && d == 1) ? R(0) : dt * u[d] * gi / (R)b.dx[d];
+        good = good && (fabs(disp[d]) < R(0.999));
+    }
+    if (valid && !good) { flag_range(err); valid = false; }
+    if (!valid) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) disp[d] = R(0);
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        if (DIM == 2 && d == 1) { c1[d] = 0; f1[d] = R(0); continue; }
+        if constexpr (P::PREC == 0) {
+            double x1 = ((double)c0[d] + f0[d]) + disp[d];
+            double fl = floor(x1);
+            c1[d] = (int)fl;
+            f1[d] = x1 - fl;
+        } else {
+            float fr = f0[d] + disp[d];
+            if (fr >= 1.0f) { c1[d] = c0[d] + 1; f1[d] = fr - 1.0f; }
+            else if (fr < 0.0f) {
+                c1[d] = c0[d] - 1; f1[d] = fr + 1.0f;
+                if (f1[d] == 1.0f) { f1[d] = 0.0f; c1[d] = c0[d]; }
+            } else { c1[d] = c0[d]; f1[d] = fr; }
+        }
+    }
+    const R wgt = valid ? ((const R *)sp.w)[i] : R(0);
+    const double dV = b.dx[0] * b.dx[1] * b.dx[2];
+    R cq[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) cq[d] = (R)(-sp.q * b.dx[d] / (b.dt * dV)) * wgt;
+    R vy = R(0);
+    if (DIM == 2) {
+        cq[1] = (R)(sp.q / dV) * wgt;
+        vy = u[1] * gi;
+    }
+    deposit_converged<DIM, QUAD, R>(lj, c0, f0, c1, f1, cq, vy, valid);
+    if (!valid) return;
+    R *uo[3] = {(R *)sp.u[0], (R *)sp.u[1], (R *)sp.u[2]};
+#pragma unroll
+    for (int d = 0; d < 3; ++d) uo[d][i] = u[d];
+    if constexpr (P::PREC == 0) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            if (DIM == 2 && d == 1) continue;
+            double x = (double)c1[d] + f1[d];
+            const double L = (double)b.n[d];
+            if (x >= L) x -= L;
+            if (x < 0.0) x += L;
+            if (x >= L) x = 0.0;
+            sp.x[d][i] = x;
+        }
+    } else {
+        int cw[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            if (DIM == 2 && d == 1) { cw[d] = 0; continue; }
+            cw[d] = wrap_index(c1[d], b.n[d]);
+            sp.off[d][i] = f1[d];
+        }
+        sp.cell[i] = cw[0] + b.n[0] * (cw[1] + b.n[1] * cw[2]);
+    }
+}
+
 // ------------------------------------------------------------ direct
 
 template <class P, int MODE>
@@ -590,7 +1003,7 @@ struct RegionWalk {
     }
 };
 
-template <int DIM, class P, int MODE>
+template <int DIM, class P, int MODE, bool QUAD>
 __device__ __forceinline__ void process_item(const KParams &prm, const Item &it, char *smem) {
     using FT = typename P::FieldT;
     using A = typename P::Acc;
@@ -657,7 +1070,26 @@ __device__ __forceinline__ void process_item(const KParams &prm, const Item &it,
     // the particles per cell the lanes of one wave sit in distinct cells and
     // their LDS atomics do not collide on one address.  S = 1 is the
     // identity.
-    {
+    if constexpr (MODE == MODE_FUSED) {
+        // every lane runs the same number of slots (the converged path)
+        const int n = it.p1 - it.p0;
+        const int S = prm.lane_stride > 1 ? prm.lane_stride : 1;
+        const int G = (n + S - 1) / S;
+        const int total = G * S;
+        const int rounds = (total + bs - 1) / bs;
+        int q = tid / G, r = tid - (tid / G) * G;
+        const int dq = bs / G, dr = bs - (bs / G) * G;
+        for (int rd = 0; rd < rounds; ++rd) {
+            const int sl = tid + rd * bs;
+            const int idx = r * S + q;
+            const bool have = sl < total && idx < n;
+            particle_converged<DIM, P, QUAD>(b, sp, (long long)(it.p0 + (have ? idx : 0)), have, tile,
+                                             lf, lj, prm.err, prm.strag_count + it.s);
+            r += dr;
+            q += dq;
+            if (r >= G) { r -= G; q += 1; }
+        }
+    } else {
         const int n = it.p1 - it.p0;
         const int S = prm.lane_stride > 1 ? prm.lane_stride : 1;
         const int G = (n + S - 1) / S;
@@ -693,7 +1125,7 @@ __device__ __forceinline__ void process_item(const KParams &prm, const Item &it,
 
 // DIMS: 3 or 2 when every box of the context has that dimensionality (one
 // code path, fewer registers), 0 for a mix.
-template <class P, int MODE, bool PERSISTENT, int DIMS>
+template <class P, int MODE, bool PERSISTENT, int DIMS, bool QUAD>
 __global__ void __launch_bounds__(P::MAX_BLOCK) k_tiled(KParams prm) {
     extern __shared__ __attribute__((aligned(16))) char smem[];
     __shared__ Item cur;
@@ -719,31 +1151,40 @@ __global__ void __launch_bounds__(P::MAX_BLOCK) k_tiled(KParams prm) {
         }
         if (it.p1 <= it.p0) continue;
         if constexpr (DIMS == 3) {
-            process_item<3, P, MODE>(prm, it, smem);
+            process_item<3, P, MODE, QUAD>(prm, it, smem);
         } else if constexpr (DIMS == 2) {
-            process_item<2, P, MODE>(prm, it, smem);
+            process_item<2, P, MODE, QUAD>(prm, it, smem);
         } else {
             const DevBox &b = prm.boxes[prm.species[it.s].box];
-            if (b.dim == 3) process_item<3, P, MODE>(prm, it, smem);
-            else process_item<2, P, MODE>(prm, it, smem);
+            if (b.dim == 3) process_item<3, P, MODE, QUAD>(prm, it, smem);
+            else process_item<2, P, MODE, QUAD>(prm, it, smem);
         }
     }
 }
 
+template <class P, int MODE, bool PERS, bool QUAD>
+hipError_t launch_tiled_q(const KParams &prm, int dims, int grid, int block, size_t lds,
+                          hipStream_t st) {
+    if (dims == 3) {
+        hipLaunchKernelGGL((k_tiled<P, MODE, PERS, 3, QUAD>), dim3(grid), dim3(block), lds, st, prm);
+    } else if (dims == 2) {
+        hipLaunchKernelGGL((k_tiled<P, MODE, PERS, 2, QUAD>), dim3(grid), dim3(block), lds, st, prm);
+    } else {
+        hipLaunchKernelGGL((k_tiled<P, MODE, PERS, 0, QUAD>), dim3(grid), dim3(block), lds, st, prm);
+    }
+    return hipGetLastError();
+}
+
+// Fused kernels: per dimensionality, with quad pooling of the deposit when
+// the lane stride is 1.  Push-only / deposit-only kernels: mixed form.
 template <class P, int MODE, bool PERS>
 hipError_t launch_tiled_dims(const KParams &prm, int dims, int grid, int block, size_t lds,
                              hipStream_t st) {
     if constexpr (MODE == MODE_FUSED) {
-        if (dims == 3) {
-            hipLaunchKernelGGL((k_tiled<P, MODE, PERS, 3>), dim3(grid), dim3(block), lds, st, prm);
-            return hipGetLastError();
-        }
-        if (dims == 2) {
-            hipLaunchKernelGGL((k_tiled<P, MODE, PERS, 2>), dim3(grid), dim3(block), lds, st, prm);
-            return hipGetLastError();
-        }
+        if (prm.lane_stride <= 1) return launch_tiled_q<P, MODE, PERS, true>(prm, dims, grid, block, lds, st);
+        return launch_tiled_q<P, MODE, PERS, false>(prm, dims, grid, block, lds, st);
     }
-    hipLaunchKernelGGL((k_tiled<P, MODE, PERS, 0>), dim3(grid), dim3(block), lds, st, prm);
+    hipLaunchKernelGGL((k_tiled<P, MODE, PERS, 0, false>), dim3(grid), dim3(block), lds, st, prm);
     return hipGetLastError();
 }
 
@@ -770,23 +1211,26 @@ hipError_t launch_prec(const KParams &prm, int form, int mode, int dims, int gri
     return launch_mode<P, MODE_FUSED>(prm, form, dims, grid, block, lds, species, st);
 }
 
-template <class P, int MODE, bool PERS, int DIMS>
+template <class P, int MODE, bool PERS, int DIMS, bool QUAD>
 hipError_t set_lds(int bytes) {
-    return hipFuncSetAttribute((const void *)&k_tiled<P, MODE, PERS, DIMS>,
+    return hipFuncSetAttribute((const void *)&k_tiled<P, MODE, PERS, DIMS, QUAD>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
 template <class P>
 hipError_t lds_limit_prec(int bytes) {
     hipError_t e = hipSuccess;
-#define PIC_SET(M, D)                                               \
-    if (e == hipSuccess) e = set_lds<P, M, false, D>(bytes);        \
-    if (e == hipSuccess) e = set_lds<P, M, true, D>(bytes);
-    PIC_SET(MODE_PUSH, 0)
-    PIC_SET(MODE_DEPOSIT, 0)
-    PIC_SET(MODE_FUSED, 0)
-    PIC_SET(MODE_FUSED, 2)
-    PIC_SET(MODE_FUSED, 3)
+#define PIC_SET(M, D, Q)                                            \
+    if (e == hipSuccess) e = set_lds<P, M, false, D, Q>(bytes);     \
+    if (e == hipSuccess) e = set_lds<P, M, true, D, Q>(bytes);
+    PIC_SET(MODE_PUSH, 0, false)
+    PIC_SET(MODE_DEPOSIT, 0, false)
+    PIC_SET(MODE_FUSED, 0, false)
+    PIC_SET(MODE_FUSED, 2, false)
+    PIC_SET(MODE_FUSED, 3, false)
+    PIC_SET(MODE_FUSED, 0, true)
+    PIC_SET(MODE_FUSED, 2, true)
+    PIC_SET(MODE_FUSED, 3, true)
 #undef PIC_SET
     return e;
 }
