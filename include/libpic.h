@@ -71,8 +71,11 @@ typedef enum {
                                since the sort stay on the LDS path; beyond
                                that they use global memory. */
     PIC_KERNEL_BATCHED = 2  /* as TILED, but a persistent grid walks a work
-                               queue of (species, tile, chunk) items so uneven
-                               tiles and many boxes share one launch */
+                               queue so uneven tiles and many boxes share one
+                               launch: one item per box tile covers every
+                               species of the box (one E/B stage, one J flush)
+                               unless they hold more than `chunk` particles
+                               together, then per-species chunks */
 } pic_kernel;
 
 typedef struct {
@@ -100,6 +103,21 @@ typedef struct {
     int32_t pad;         /* 0: pad the row of the LDS current tile so a
                             wave's lanes hit distinct LDS banks (when it
                             fits); -1: no padding */
+    int32_t cell_order;  /* Order of the particles inside a tile after
+                            pic_sort_tiles.  -1: previous order (tile id
+                            only).  1: by class (lx+ly+lz) mod 4 of the
+                            tile-local cell (lx,ly,lz), then by the cell
+                            lx + tx*(ly + ty*lz), ties stable: cells of one
+                            class that share a row differ by a multiple of 4
+                            along it, so consecutive particles of different
+                            cells never deposit onto one LDS address.  2: as
+                            1, then each tile stably split into the whole
+                            groups of four of every cell followed by each
+                            cell's last (count mod 4) particles, so that
+                            aligned groups of four share a cell (the quad
+                            pooling of the deposit at lane_stride 1).  1 and
+                            2 apply when tile id and cell fit a 31-bit key.
+                            0 = default: 2 for BATCHED, else -1. */
 } pic_tuning;
 
 typedef struct {
@@ -134,7 +152,8 @@ pic_status pic_init(pic_ctx **ctx, const pic_box_desc *boxes, int32_t nboxes,
 /* Per-tile stable counting sort (least-significant-digit radix passes over
  * the tile id): every species' particle arrays are permuted IN PLACE so that
  * particles are grouped by tile id = tx + ntx*(ty + nty*tz) of their cell,
- * ties kept in their previous order.  The per-tile offsets are kept in the
+ * ties kept in their previous order (with pic_tuning.cell_order, ordered by
+ * cell inside each tile first).  The per-tile offsets are kept in the
  * context for the tiled kernels.  Optional outputs, each an array of nsp
  * device pointers (the array itself on the host; it or any entry may be
  * NULL): perm_out[s][i] = previous index of the particle now at i;

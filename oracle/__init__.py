@@ -75,6 +75,9 @@ def lib():
         L.orc_kinetic_energy.restype = _D
         L.orc_tile_keys.argtypes = [C.POINTER(Grid), _P, C.POINTER(Species), _P]
         L.orc_stable_sort.argtypes = [C.c_int64, _P, _I, _P, _P, _P]
+        L.orc_cell_order_keys.argtypes = [C.POINTER(Grid), _P, _I, C.POINTER(Species), _P]
+        L.orc_stable_perm.argtypes = [C.c_int64, _P, _P]
+        L.orc_quad_order.argtypes = [C.c_int64, _P, _I, _P]
         _lib = L
     return _lib
 
@@ -222,6 +225,30 @@ def tile_keys(g: Grid, tile, sp):
     key = np.zeros(st.np, dtype=np.int32)
     lib().orc_tile_keys(C.byref(g), t.ctypes.data, C.byref(st), key.ctypes.data)
     return key
+
+
+def cell_order_keys(g: Grid, tile, cbits, sp):
+    """Within-tile cell-order sort keys (int64), see orc_cell_order_keys."""
+    st = _species_struct(sp)
+    t = np.ascontiguousarray(tile, dtype=np.int32)
+    key = np.zeros(st.np, dtype=np.int64)
+    lib().orc_cell_order_keys(C.byref(g), t.ctypes.data, int(cbits), C.byref(st), key.ctypes.data)
+    return key
+
+
+def stable_perm(key):
+    key = np.ascontiguousarray(key, dtype=np.int64)
+    perm = np.zeros(key.shape[0], dtype=np.int32)
+    lib().orc_stable_perm(key.shape[0], key.ctypes.data, perm.ctypes.data)
+    return perm
+
+
+def quad_order(key, cbits):
+    """Cell order with each tile's whole groups of four first (int32 perm)."""
+    key = np.ascontiguousarray(key, dtype=np.int64)
+    perm = np.zeros(key.shape[0], dtype=np.int32)
+    lib().orc_quad_order(key.shape[0], key.ctypes.data, int(cbits), perm.ctypes.data)
+    return perm
 
 
 def stable_sort(key, nkeys):

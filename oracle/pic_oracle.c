@@ -440,6 +440,71 @@ static int by_key_then_index(const void *a, const void *b)
     return ia < ib ? -1 : (ia > ib ? 1 : 0);
 }
 
+void orc_cell_order_keys(const orc_grid *g, const int32_t tile[3], int32_t cbits,
+                         const orc_species *S, int64_t *key)
+{
+    int64_t nt[3];
+    for (int d = 0; d < 3; ++d) nt[d] = (g->n[d] + tile[d] - 1) / tile[d];
+    const int64_t t1 = g->dim == 3 ? tile[1] : 1;
+    for (int64_t p = 0; p < S->np; ++p) {
+        int64_t t[3], l[3];
+        for (int d = 0; d < 3; ++d) {
+            if (g->dim == 2 && d == 1) { t[d] = 0; l[d] = 0; continue; }
+            int64_t c = wrapi((int64_t)floor(S->x[d][p]), g->n[d]);
+            t[d] = c / tile[d];
+            l[d] = c - t[d] * tile[d];
+        }
+        const int64_t id = t[0] + nt[0] * (t[1] + nt[1] * t[2]);
+        const int64_t cls = (l[0] + l[1] + l[2]) % 4;
+        const int64_t within = l[0] + tile[0] * (l[1] + t1 * l[2]);
+        key[p] = (id << (cbits + 2)) | (cls << cbits) | within;
+    }
+}
+
+static const int64_t *g_sort_key64;
+
+static int by_key64_then_index(const void *a, const void *b)
+{
+    int32_t ia = *(const int32_t *)a, ib = *(const int32_t *)b;
+    int64_t ka = g_sort_key64[ia], kb = g_sort_key64[ib];
+    if (ka != kb) return ka < kb ? -1 : 1;
+    return ia < ib ? -1 : (ia > ib ? 1 : 0);
+}
+
+void orc_stable_perm(int64_t np, const int64_t *key, int32_t *perm)
+{
+    for (int64_t p = 0; p < np; ++p) perm[p] = (int32_t)p;
+    g_sort_key64 = key;
+    qsort(perm, (size_t)np, sizeof(int32_t), by_key64_then_index);
+}
+
+void orc_quad_order(int64_t np, const int64_t *key, int32_t cbits, int32_t *perm)
+{
+    int32_t *sorted = (int32_t *)malloc(sizeof(int32_t) * (size_t)(np > 0 ? np : 1));
+    char *rest = (char *)malloc((size_t)(np > 0 ? np : 1));
+    orc_stable_perm(np, key, sorted);
+    /* runs of equal keys: mark each cell's last count mod 4 */
+    for (int64_t a = 0; a < np;) {
+        int64_t b = a;
+        while (b < np && key[sorted[b]] == key[sorted[a]]) ++b;
+        const int64_t cnt = b - a;
+        for (int64_t i = a; i < b; ++i) rest[i] = (i - a) >= cnt - cnt % 4;
+        a = b;
+    }
+    /* per tile: whole groups first, then the rest */
+    int64_t out = 0;
+    for (int64_t a = 0; a < np;) {
+        const int64_t tile = key[sorted[a]] >> (cbits + 2);
+        int64_t b = a;
+        while (b < np && (key[sorted[b]] >> (cbits + 2)) == tile) ++b;
+        for (int64_t i = a; i < b; ++i) if (!rest[i]) perm[out++] = sorted[i];
+        for (int64_t i = a; i < b; ++i) if (rest[i]) perm[out++] = sorted[i];
+        a = b;
+    }
+    free(rest);
+    free(sorted);
+}
+
 void orc_stable_sort(int64_t np, const int32_t *key, int32_t nkeys,
                      int32_t *perm, int32_t *count, int32_t *offset)
 {

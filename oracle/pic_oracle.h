@@ -116,6 +116,25 @@ void orc_tile_keys(const orc_grid *g, const int32_t tile[3],
 void orc_stable_sort(int64_t np, const int32_t *key, int32_t nkeys,
                      int32_t *perm, int32_t *count, int32_t *offset);
 
+/* Within-tile cell order of the tiled sort: for the particle's cell with
+ * tile-local coordinates (lx, ly, lz) (ly = 0 in 2D), key = tile id
+ * << (cbits + 2) | ((lx + ly + lz) mod 4) << cbits | (lx + tile[0]*(ly +
+ * t1*lz)), t1 = tile[1] in 3D and 1 in 2D.  A layout choice of the GPU
+ * sort, not part of the method: sorting by it groups a tile's particles by
+ * cell class, then cell. */
+void orc_cell_order_keys(const orc_grid *g, const int32_t tile[3], int32_t cbits,
+                         const orc_species *sp, int64_t *key);
+
+/* Stable sort of particle indices by a 64-bit key (ties in index order). */
+void orc_stable_perm(int64_t np, const int64_t *key, int32_t *perm);
+
+/* The cell order followed by a stable split of every tile (tile id = key >>
+ * (cbits + 2)): first, in sorted order, the particles of each cell's whole
+ * groups of four (the first count - count mod 4 of its run), then the
+ * remaining count mod 4 of every cell, also in sorted order.  Also a layout
+ * choice of the GPU sort. */
+void orc_quad_order(int64_t np, const int64_t *key, int32_t cbits, int32_t *perm);
+
 #ifdef __cplusplus
 }
 #endif

@@ -38,7 +38,8 @@ class pic_box_desc(C.Structure):
 
 class pic_tuning(C.Structure):
     _fields_ = [("kernel", C.c_int32), ("block", C.c_int32), ("chunk", C.c_int32),
-                ("wg_per_cu", C.c_int32), ("lane_stride", C.c_int32), ("pad", C.c_int32)]
+                ("wg_per_cu", C.c_int32), ("lane_stride", C.c_int32), ("pad", C.c_int32),
+                ("cell_order", C.c_int32)]
 
 
 class pic_fields(C.Structure):
@@ -178,18 +179,18 @@ class DeviceSpecies:
 
 
 def make_species(p, precision: int, box: int = None, device="cuda") -> DeviceSpecies:
-    """Device copy of a ``pic_inputs.Particles`` in the requested form."""
+    """Device copy of a ``pic_inputs.Particles`` in the requested form (always
+    new storage: the kernels update it in place)."""
     b = p.box if box is None else box
+
+    def cp(t, dt):
+        return t.to(device=device, dtype=dt, copy=True).contiguous()
+
     if precision == PIC_FP64:
-        return DeviceSpecies(p.q, p.m, b, precision,
-                             p.u.to(device=device, dtype=torch.float64).contiguous(),
-                             p.w.to(device=device, dtype=torch.float64).contiguous(),
-                             x=p.x.to(device=device, dtype=torch.float64).contiguous())
-    return DeviceSpecies(p.q, p.m, b, precision,
-                         p.u.to(device=device, dtype=torch.float32).contiguous(),
-                         p.w.to(device=device, dtype=torch.float32).contiguous(),
-                         cell=p.cell.to(device=device, dtype=torch.int32).contiguous(),
-                         off=p.off.to(device=device, dtype=torch.float32).contiguous())
+        return DeviceSpecies(p.q, p.m, b, precision, cp(p.u, torch.float64), cp(p.w, torch.float64),
+                             x=cp(p.x, torch.float64))
+    return DeviceSpecies(p.q, p.m, b, precision, cp(p.u, torch.float32), cp(p.w, torch.float32),
+                         cell=cp(p.cell, torch.int32), off=cp(p.off, torch.float32))
 
 
 def _species_array(species: Sequence[DeviceSpecies]):
@@ -207,7 +208,8 @@ def _ptr_array(ts):
 # ------------------------------------------------------------------ C ABI names
 
 def pic_init(boxes, precision: int, stream=None, kernel: Optional[int] = None, block: int = 0,
-             chunk: int = 0, wg_per_cu: int = 0, lane_stride: int = 0, pad: int = 0):
+             chunk: int = 0, wg_per_cu: int = 0, lane_stride: int = 0, pad: int = 0,
+             cell_order: int = 0):
     """boxes: objects with dim, n, dx, dt, order, tile (``pic_inputs.Box``).
     Returns an opaque context handle (int)."""
     descs = (pic_box_desc * len(boxes))()
@@ -224,13 +226,14 @@ def pic_init(boxes, precision: int, stream=None, kernel: Optional[int] = None, b
         d.cell_base = base
         base += b.ncells
     tun = None
-    if kernel is not None or block or chunk or wg_per_cu or lane_stride or pad:
+    if kernel is not None or block or chunk or wg_per_cu or lane_stride or pad or cell_order:
         tun = pic_tuning()
         tun.kernel = (PIC_KERNEL_TILED if precision == PIC_FP64 else PIC_KERNEL_BATCHED) \
             if kernel is None else kernel
         tun.block, tun.chunk, tun.wg_per_cu = block, chunk, wg_per_cu
         tun.lane_stride = lane_stride
         tun.pad = pad
+        tun.cell_order = cell_order
     if stream is None:
         stream = torch.cuda.current_stream().cuda_stream
     h = C.c_void_p()

@@ -103,9 +103,16 @@ struct pic_ctx {
     int dsp_cap = 0;
     std::vector<int> hprefix;
     int *dprefix = nullptr;
-    int nslots = 0;
+    int nslots = 0;                 // (species, tile) slots of the tiled form
+    // species of each box (CSR) and the boxes' tile-count prefix: the
+    // box-tile slots the batched form builds its work items over
+    std::vector<int> hbox_sp_off, hbox_sp;
+    int *dbox_sp_off = nullptr, *dbox_sp = nullptr;
+    int *dbprefix = nullptr;
+    int nbslots = 0;
     // sort scratch
     long long sort_cap = 0;
+    int *sort_tot = nullptr;        // 2 device ints of the quads-first pass
     int *keys[2] = {nullptr, nullptr};
     int *vals[2] = {nullptr, nullptr};
     void *tmp = nullptr;
@@ -283,10 +290,14 @@ pic_status bind_species(pic_ctx *c, const pic_species *sp, int nsp, bool need_pu
             dfree(c->dsp);
             dfree(c->dprefix);
             dfree(c->strag_count);
+            dfree(c->dbox_sp);
+            c->hbox_sp.clear();
+            c->hbox_sp_off.clear();
             int cap = nsp + 8;
             if ((st = dalloc(&c->dsp, (size_t)cap)) != PIC_OK) return st;
             if ((st = dalloc(&c->dprefix, (size_t)cap + 1)) != PIC_OK) return st;
             if ((st = dalloc(&c->strag_count, (size_t)cap)) != PIC_OK) return st;
+            if ((st = dalloc(&c->dbox_sp, (size_t)cap)) != PIC_OK) return st;
             c->dsp_cap = cap;
         }
         if (nsp > 0) {
@@ -297,6 +308,22 @@ pic_status bind_species(pic_ctx *c, const pic_species *sp, int nsp, bool need_pu
         c->hprefix = prefix;
     }
     c->nslots = prefix[nsp];
+    std::vector<int> bso(c->nboxes + 1, 0), bsl(std::max(nsp, 1), 0);
+    for (int s = 0; s < nsp; ++s) ++bso[sp[s].box + 1];
+    for (int b = 0; b < c->nboxes; ++b) bso[b + 1] += bso[b];
+    {
+        std::vector<int> fill(bso.begin(), bso.end() - 1);
+        for (int s = 0; s < nsp; ++s) bsl[fill[sp[s].box]++] = s;
+    }
+    bsl.resize(nsp);
+    if (bso != c->hbox_sp_off || bsl != c->hbox_sp) {
+        if (c->capturing) return fail(PIC_ERR_STATE, "species binding changed during graph capture");
+        (void)hipStreamSynchronize(c->stream);
+        HIP_TRY(hipMemcpy(c->dbox_sp_off, bso.data(), (c->nboxes + 1) * sizeof(int), hipMemcpyHostToDevice));
+        if (nsp > 0) HIP_TRY(hipMemcpy(c->dbox_sp, bsl.data(), nsp * sizeof(int), hipMemcpyHostToDevice));
+        c->hbox_sp_off = bso;
+        c->hbox_sp = bsl;
+    }
     return PIC_OK;
 }
 
@@ -323,6 +350,8 @@ KParams make_params(pic_ctx *c, const pic_fields *f, int nsp) {
     k.margin = c->margin;
     k.jrow = c->jrow;
     k.strag_count = c->strag_count;
+    k.box_sp_off = c->dbox_sp_off;
+    k.box_sp = c->dbox_sp;
     return k;
 }
 
@@ -409,7 +438,8 @@ pic_status ensure_sort_scratch(pic_ctx *c, long long np, long long nitems_cap) {
     }
     size_t need_counts = (size_t)radix_blocks(np) * 256 + 256;
     size_t need_scan = std::max(scan_scratch_ints((long long)need_counts),
-                                scan_scratch_ints((long long)c->nslots + 1));
+                                scan_scratch_ints((long long)c->nbslots + 1));
+    if (c->tun.cell_order == 2) need_scan = std::max(need_scan, scan_scratch_ints(np));
     if (c->counts_cap < need_counts) {
         if (c->capturing) return fail(PIC_ERR_STATE, "scratch growth during graph capture");
         (void)hipStreamSynchronize(c->stream);
@@ -425,12 +455,12 @@ pic_status ensure_sort_scratch(pic_ctx *c, long long np, long long nitems_cap) {
         c->scan_cap = need_scan;
     }
     if (c->tun.kernel == PIC_KERNEL_BATCHED) {
-        if (c->item_slot_cap < c->nslots + 1) {
+        if (c->item_slot_cap < c->nbslots + 1) {
             if (c->capturing) return fail(PIC_ERR_STATE, "scratch growth during graph capture");
             (void)hipStreamSynchronize(c->stream);
             dfree(c->item_counts);
             dfree(c->item_starts);
-            int cap = c->nslots + 64;
+            int cap = c->nbslots + 64;
             if ((st = dalloc(&c->item_counts, (size_t)cap)) != PIC_OK) return st;
             if ((st = dalloc(&c->item_starts, (size_t)cap)) != PIC_OK) return st;
             c->item_slot_cap = cap;
@@ -466,8 +496,16 @@ pic_status do_sort(pic_ctx *c, const pic_species *sp, int nsp, int32_t *const *p
         const long long np = p.np;
         const int nkeys = b.ntiles + 1;
         Slot &sl = c->slots[s];
-        HIP_TRY(launch_tile_keys(prec, c->dsp, s, np, c->dbox, c->keys[0], c->vals[0], c->derr, S));
-        const int passes = (key_bits(nkeys) + 7) / 8;
+        // cell bits of the within-tile order (0: tile id only)
+        int cb = 0;
+        if (c->tun.cell_order) {
+            const int vol = b.tile[0] * (b.dim == 3 ? b.tile[1] : 1) * b.tile[2];
+            cb = key_bits(vol);
+            if (key_bits(nkeys) + cb + 2 > 31) cb = 0;
+        }
+        const int shift = cb ? cb + 2 : 0;
+        HIP_TRY(launch_tile_keys(prec, c->dsp, s, np, c->dbox, cb, c->keys[0], c->vals[0], c->derr, S));
+        const int passes = (key_bits(nkeys) + shift + 7) / 8;
         int cur = 0;
         for (int ps = 0; ps < passes; ++ps) {
             HIP_TRY(radix_pass(c->keys[cur], c->vals[cur], c->keys[1 - cur], c->vals[1 - cur], np,
@@ -475,7 +513,12 @@ pic_status do_sort(pic_ctx *c, const pic_species *sp, int nsp, int32_t *const *p
             cur = 1 - cur;
         }
         const int *perm = c->vals[cur];
-        HIP_TRY(launch_tile_offsets(c->keys[cur], np, nkeys, sl.tile_off, S));
+        HIP_TRY(launch_tile_offsets(c->keys[cur], np, nkeys, shift, sl.tile_off, S));
+        if (cb && c->tun.cell_order == 2) {
+            HIP_TRY(quads_first(c->keys[cur], c->vals[cur], np, shift, sl.tile_off, c->keys[1 - cur],
+                                (int *)c->tmp, c->vals[1 - cur], c->sort_tot, c->scan_scr, S));
+            perm = c->vals[1 - cur];
+        }
         // permute the particle arrays in place through the tmp buffer
         auto perm8 = [&](void *a) -> hipError_t {
             hipError_t e = launch_gather8(a, perm, c->tmp, np, S);
@@ -505,12 +548,13 @@ pic_status do_sort(pic_ctx *c, const pic_species *sp, int nsp, int32_t *const *p
             }
         }
         if (perm_out && perm_out[s]) HIP_TRY(launch_copy4(perm, perm_out[s], np, S));
-        if (key_out && key_out[s]) HIP_TRY(launch_copy4(c->keys[cur], key_out[s], np, S));
+        if (key_out && key_out[s]) HIP_TRY(launch_shift_copy(c->keys[cur], key_out[s], np, shift, S));
         if (off_out && off_out[s]) HIP_TRY(launch_copy4(sl.tile_off, off_out[s], b.ntiles + 1, S));
         sl.sorted = true;
     }
-    if (c->tun.kernel == PIC_KERNEL_BATCHED && c->nslots > 0) {
-        HIP_TRY(launch_items(c->dsp, c->dprefix, nsp, c->nslots, c->tun.chunk, c->item_counts,
+    if (c->tun.kernel == PIC_KERNEL_BATCHED && c->nbslots > 0) {
+        HIP_TRY(launch_items(c->dsp, c->dbprefix, c->nboxes, c->dbox_sp_off, c->dbox_sp, c->nbslots,
+                             c->tun.chunk, c->item_counts,
                              c->item_starts, c->scan_scr, c->items, c->nitems, c->queue, S));
     }
     return PIC_OK;
@@ -564,6 +608,7 @@ pic_status pic_init(pic_ctx **out, const pic_box_desc *boxes, int32_t nboxes, pi
     t.wg_per_cu = 2;
     t.lane_stride = 1;
     t.pad = 0;
+    t.cell_order = 0;
     if (tuning) {
         t.kernel = tuning->kernel;
         if (tuning->block) t.block = tuning->block;
@@ -571,6 +616,7 @@ pic_status pic_init(pic_ctx **out, const pic_box_desc *boxes, int32_t nboxes, pi
         if (tuning->wg_per_cu) t.wg_per_cu = tuning->wg_per_cu;
         if (tuning->lane_stride) t.lane_stride = tuning->lane_stride;
         t.pad = tuning->pad;
+        t.cell_order = tuning->cell_order;
     }
     if (t.kernel < 0 || t.kernel > 2) return fail(PIC_ERR_ARG, "bad kernel form");
     const int max_block = prec == PIC_FP64 ? 512 : 1024;
@@ -579,6 +625,8 @@ pic_status pic_init(pic_ctx **out, const pic_box_desc *boxes, int32_t nboxes, pi
     if (t.chunk < 1) return fail(PIC_ERR_ARG, "chunk must be >= 1");
     if (t.wg_per_cu < 1 || t.wg_per_cu > 64) return fail(PIC_ERR_ARG, "wg_per_cu must be 1..64");
     if (t.lane_stride < 1 || t.lane_stride > 64) return fail(PIC_ERR_ARG, "lane_stride must be 1..64");
+    if (t.cell_order < -1 || t.cell_order > 2) return fail(PIC_ERR_ARG, "cell_order must be -1..2");
+    t.cell_order = t.cell_order == 0 ? (t.kernel == PIC_KERNEL_BATCHED ? 2 : 0) : std::max(t.cell_order, 0);
 
     pic_ctx *c = new pic_ctx();
     c->nboxes = nboxes;
@@ -682,9 +730,21 @@ pic_status pic_init(pic_ctx **out, const pic_box_desc *boxes, int32_t nboxes, pi
     if ((st = dalloc(&c->dbox, (size_t)nboxes)) != PIC_OK ||
         (st = dalloc(&c->dfp, (size_t)nboxes + 1)) != PIC_OK ||
         (st = dalloc(&c->derr, 4)) != PIC_OK || (st = dalloc(&c->nitems, 4)) != PIC_OK ||
-        (st = dalloc(&c->queue, 4)) != PIC_OK) {
+        (st = dalloc(&c->queue, 4)) != PIC_OK ||
+        (st = dalloc(&c->dbox_sp_off, (size_t)nboxes + 1)) != PIC_OK ||
+        (st = dalloc(&c->dbprefix, (size_t)nboxes + 1)) != PIC_OK ||
+        (st = dalloc(&c->sort_tot, 4)) != PIC_OK) {
         pic_free(c);
         return st;
+    }
+    {
+        std::vector<int> bp(nboxes + 1, 0);
+        for (int i = 0; i < nboxes; ++i) bp[i + 1] = bp[i] + c->hbox[i].ntiles;
+        c->nbslots = bp[nboxes];
+        if (hipMemcpy(c->dbprefix, bp.data(), (nboxes + 1) * sizeof(int), hipMemcpyHostToDevice) != hipSuccess) {
+            pic_free(c);
+            return fail(PIC_ERR_DEVICE, "upload of box tables failed");
+        }
     }
     if (hipMemcpy(c->dbox, c->hbox.data(), nboxes * sizeof(DevBox), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(c->dfp, c->hfp.data(), (nboxes + 1) * sizeof(long long), hipMemcpyHostToDevice) != hipSuccess) {
@@ -851,6 +911,10 @@ pic_status pic_free(pic_ctx *c) {
     dfree(c->queue);
     dfree(c->dsp);
     dfree(c->dprefix);
+    dfree(c->dbox_sp);
+    dfree(c->dbox_sp_off);
+    dfree(c->dbprefix);
+    dfree(c->sort_tot);
     dfree(c->dbox);
     dfree(c->dfp);
     dfree(c->derr);

@@ -5,22 +5,37 @@
 
 namespace pic {
 
+// Sort keys: the tile id, or with cbits > 0 (tile id, cell class, cell in
+// tile) packed as tile << (cbits + 2) | class << cbits | cell.
 hipError_t launch_tile_keys(int prec, const DevSpecies *spt, int s, long long np,
-                            const DevBox *boxes, int *key, int *val, int *err, hipStream_t st);
+                            const DevBox *boxes, int cbits, int *key, int *val, int *err,
+                            hipStream_t st);
 size_t scan_scratch_ints(long long n);
 hipError_t scan_exclusive(const int *in, int *out, long long n, int *total, int *scratch,
                           hipStream_t st);
 int radix_blocks(long long n);
 hipError_t radix_pass(const int *kin, const int *vin, int *kout, int *vout, long long n,
                       int shift, int *counts, int *scan_scratch, hipStream_t st);
-hipError_t launch_tile_offsets(const int *key, long long n, int nkeys, int *off, hipStream_t st);
+hipError_t launch_tile_offsets(const int *key, long long n, int nkeys, int shift, int *off,
+                              hipStream_t st);
+hipError_t launch_shift_copy(const int *src, int *dst, long long n, int shift, hipStream_t st);
+// Stable reorder of each tile's cell-ordered particles: whole groups of four
+// of a cell first, each cell's last (count mod 4) after them.  key: sorted
+// keys (tile = key >> shift), perm_in: their source indices; perm_out gets
+// the reordered source indices.  Scratch: work (n ints), work2 (2n ints),
+// totals (2 ints); perm_out must not alias the inputs.
+hipError_t quads_first(const int *key, const int *perm_in, long long n, int shift,
+                       const int *tile_off, int *work, int *work2, int *perm_out, int *totals,
+                       int *scan_scratch, hipStream_t st);
 hipError_t launch_gather4(const void *src, const int *perm, void *dst, long long n, hipStream_t st);
 hipError_t launch_gather8(const void *src, const int *perm, void *dst, long long n, hipStream_t st);
 hipError_t launch_copy4(const void *src, void *dst, long long n, hipStream_t st);
 hipError_t launch_copy8(const void *src, void *dst, long long n, hipStream_t st);
-hipError_t launch_items(const DevSpecies *spt, const int *prefix, int nsp, int nslots, int chunk,
-                        int *counts, int *starts, int *scan_scratch, Item *items, int *nitems,
-                        int *queue, hipStream_t st);
+// Work items of the batched kernel over the box-tile slots (bprefix: nb + 1
+// tile-count prefix over the boxes; box_sp_off / box_sp: species per box).
+hipError_t launch_items(const DevSpecies *spt, const int *bprefix, int nb, const int *box_sp_off,
+                        const int *box_sp, int nslots, int chunk, int *counts, int *starts,
+                        int *scan_scratch, Item *items, int *nitems, int *queue, hipStream_t st);
 hipError_t launch_set_int(int *p, int v, hipStream_t st);
 hipError_t launch_zero_ints(int *p, int n, hipStream_t st);
 hipError_t launch_zero_j(const DevFields &f, const DevBox *boxes, const long long *fp, int nb,

@@ -23,8 +23,8 @@ __device__ inline int wave_id() { return threadIdx.x >> 6; }
 // ------------------------------------------------------------ keys
 
 template <int PREC>
-__global__ void k_tile_keys(const DevSpecies *spt, int s, const DevBox *boxes, int *key,
-                            int *val, int *err) {
+__global__ void k_tile_keys(const DevSpecies *spt, int s, const DevBox *boxes, int cbits,
+                            int *key, int *val, int *err) {
     const DevSpecies &sp = spt[s];
     const DevBox &b = boxes[sp.box];
     long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -52,9 +52,17 @@ __global__ void k_tile_keys(const DevSpecies *spt, int s, const DevBox *boxes, i
     }
     int k;
     if (ok) {
-        k = c[0] / b.tile[0] + b.nt[0] * (c[1] / b.tile[1] + b.nt[1] * (c[2] / b.tile[2]));
+        const int tx = c[0] / b.tile[0], ty = c[1] / b.tile[1], tz = c[2] / b.tile[2];
+        k = tx + b.nt[0] * (ty + b.nt[1] * tz);
+        if (cbits > 0) {
+            const int lx = c[0] - tx * b.tile[0], ly = c[1] - ty * b.tile[1],
+                      lz = c[2] - tz * b.tile[2];
+            const int within = lx + b.tile[0] * (ly + (b.dim == 3 ? b.tile[1] : 1) * lz);
+            k = (k << (cbits + 2)) | (((lx + ly + lz) & 3) << cbits) | within;
+        }
     } else {
-        k = b.ntiles;       // bucket of invalid particles, after every tile
+        // bucket of invalid particles, after every tile
+        k = cbits > 0 ? (b.ntiles << (cbits + 2)) : b.ntiles;
         atomicOr(err, 1);
     }
     key[i] = k;
@@ -128,13 +136,70 @@ __global__ void __launch_bounds__(SBS) k_radix_down(const int *key_in, const int
     }
 }
 
-// offsets[t] = first sorted position whose key is >= t, t = 0 .. nkeys.
-__global__ void k_tile_offsets(const int *key, long long n, int nkeys, int *off) {
+// offsets[t] = first sorted position whose tile (key >> shift) is >= t,
+// t = 0 .. nkeys.
+__global__ void k_tile_offsets(const int *key, long long n, int nkeys, int shift, int *off) {
     long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i > n) return;
-    int prev = (i == 0) ? -1 : key[i - 1];
-    int cur = (i == n) ? nkeys : key[i];
+    int prev = (i == 0) ? -1 : (key[i - 1] >> shift);
+    int cur = (i == n) ? nkeys : (key[i] >> shift);
     for (int t = prev + 1; t <= cur; ++t) off[t] = (int)i;
+}
+
+__global__ void k_shift_copy(const int *src, int *dst, long long n, int shift) {
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[i] >> shift;
+}
+
+// ------------------------------------------------------------ quads first
+//
+// After the cell-ordered sort, the particles of one cell form a run of equal
+// keys.  Each tile's particles are reordered (stably) so that the runs'
+// whole groups of four come first and the last (count mod 4) particles of
+// every run after them: every aligned group of four in the first part then
+// shares one cell.
+
+__device__ inline int run_head(const int *key, long long i) {
+    return (i == 0 || key[i] != key[i - 1]) ? 1 : 0;
+}
+
+__global__ void k_run_heads(const int *key, long long n, int *h) {
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) h[i] = run_head(key, i);
+}
+
+// heads_excl: exclusive scan of the heads, i.e. the run index of a head.
+__global__ void k_run_starts(const int *key, long long n, const int *heads_excl, int *starts) {
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && run_head(key, i)) starts[heads_excl[i]] = (int)i;
+}
+
+__global__ void k_quad_flags(const int *key, long long n, const int *heads_excl, const int *starts,
+                             const int *nruns, int *flag) {
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int r = heads_excl[i] + run_head(key, i) - 1;
+    const long long start = starts[r];
+    const long long end = r + 1 < *nruns ? starts[r + 1] : n;
+    const long long cnt = end - start;
+    flag[i] = (i - start) >= cnt - (cnt & 3) ? 1 : 0;
+}
+
+// Final position of sorted element i inside its tile [o0, o1): unflagged
+// elements first, flagged after them, each in sorted order.
+__global__ void k_quad_scatter(const int *key, long long n, int shift, const int *tile_off,
+                               const int *flag, const int *fexcl, const int *ftotal,
+                               const int *perm_in, int *perm_out) {
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int t = key[i] >> shift;
+    const long long o0 = tile_off[t], o1 = tile_off[t + 1];
+    const int g0 = fexcl[o0];
+    const int g1 = o1 < n ? fexcl[o1] : *ftotal;
+    const long long fb = fexcl[i] - g0;
+    const long long unflagged = (o1 - o0) - (g1 - g0);
+    const long long pos = flag[i] ? o0 + unflagged + fb : i - fb;
+    perm_out[pos] = perm_in[i];
 }
 
 // ------------------------------------------------------------ scan
@@ -204,35 +269,65 @@ __global__ void k_copy(const T *src, T *dst, long long n) {
 
 // ------------------------------------------------------------ work items
 
-__device__ inline int slot_species(const int *prefix, int nsp, int g) {
-    int s = 0;
-    while (s + 1 < nsp && prefix[s + 1] <= g) ++s;
-    return s;
+// Box-tile slots: slot g is tile g - prefix[b] of box b (prefix over the
+// boxes' tile counts, nb + 1 entries).
+__device__ inline int slot_box(const int *prefix, int nb, int g) {
+    int lo = 0, hi = nb - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (prefix[mid] <= g) lo = mid; else hi = mid - 1;
+    }
+    return lo;
 }
 
-__global__ void k_item_count(const DevSpecies *spt, const int *prefix, int nsp, int nslots,
-                             int chunk, int *counts) {
-    int g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= nslots) return;
-    int s = slot_species(prefix, nsp, g);
-    int t = g - prefix[s];
-    const int *off = spt[s].tile_off;
-    int n = off[t + 1] - off[t];
-    counts[g] = (n + chunk - 1) / chunk;
+// Items of one box tile: none if it is empty, one item over all its species
+// if they hold at most `chunk` particles together, else chunks of at most
+// `chunk` particles of one species each.
+struct TileItems {
+    int total, chunks;
+};
+
+__device__ inline TileItems tile_items(const DevSpecies *spt, const int *box_sp_off,
+                                       const int *box_sp, int b, int t, int chunk) {
+    TileItems r{0, 0};
+    for (int k = box_sp_off[b]; k < box_sp_off[b + 1]; ++k) {
+        const int *off = spt[box_sp[k]].tile_off;
+        const int n = off[t + 1] - off[t];
+        r.total += n;
+        r.chunks += (n + chunk - 1) / chunk;
+    }
+    return r;
 }
 
-__global__ void k_item_fill(const DevSpecies *spt, const int *prefix, int nsp, int nslots,
-                            int chunk, const int *starts, Item *items) {
+__global__ void k_item_count(const DevSpecies *spt, const int *bprefix, int nb,
+                             const int *box_sp_off, const int *box_sp, int nslots, int chunk,
+                             int *counts) {
     int g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= nslots) return;
-    int s = slot_species(prefix, nsp, g);
-    int t = g - prefix[s];
-    const int *off = spt[s].tile_off;
-    int p0 = off[t], p1 = off[t + 1];
+    const int b = slot_box(bprefix, nb, g);
+    const TileItems ti = tile_items(spt, box_sp_off, box_sp, b, g - bprefix[b], chunk);
+    counts[g] = ti.total == 0 ? 0 : (ti.total <= chunk ? 1 : ti.chunks);
+}
+
+__global__ void k_item_fill(const DevSpecies *spt, const int *bprefix, int nb,
+                            const int *box_sp_off, const int *box_sp, int nslots, int chunk,
+                            const int *starts, Item *items) {
+    int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= nslots) return;
+    const int b = slot_box(bprefix, nb, g);
+    const int t = g - bprefix[b];
+    const TileItems ti = tile_items(spt, box_sp_off, box_sp, b, t, chunk);
     int st = starts[g];
-    for (int c = 0; p0 + c * chunk < p1; ++c) {
-        int a = p0 + c * chunk;
-        items[st + c] = Item{s, t, a, min(p1, a + chunk)};
+    if (ti.total == 0) return;
+    if (ti.total <= chunk) {
+        items[st] = Item{-1 - b, t, 0, ti.total};
+        return;
+    }
+    for (int k = box_sp_off[b]; k < box_sp_off[b + 1]; ++k) {
+        const int s = box_sp[k];
+        const int *off = spt[s].tile_off;
+        const int p0 = off[t], p1 = off[t + 1];
+        for (int a = p0; a < p1; a += chunk) items[st++] = Item{s, t, a, min(p1, a + chunk)};
     }
 }
 
@@ -353,14 +448,15 @@ inline unsigned blocks_for(long long n, int bs) { return (unsigned)((n + bs - 1)
 // ============================================================ host launchers
 
 hipError_t launch_tile_keys(int prec, const DevSpecies *spt, int s, long long np,
-                            const DevBox *boxes, int *key, int *val, int *err, hipStream_t st) {
+                            const DevBox *boxes, int cbits, int *key, int *val, int *err,
+                            hipStream_t st) {
     if (np == 0) return hipSuccess;
     if (prec == 0)
         hipLaunchKernelGGL(k_tile_keys<0>, dim3(blocks_for(np, 256)), dim3(256), 0, st, spt, s,
-                           boxes, key, val, err);
+                           boxes, cbits, key, val, err);
     else
         hipLaunchKernelGGL(k_tile_keys<1>, dim3(blocks_for(np, 256)), dim3(256), 0, st, spt, s,
-                           boxes, key, val, err);
+                           boxes, cbits, key, val, err);
     return hipGetLastError();
 }
 
@@ -418,9 +514,38 @@ hipError_t radix_pass(const int *kin, const int *vin, int *kout, int *vout, long
     return hipGetLastError();
 }
 
-hipError_t launch_tile_offsets(const int *key, long long n, int nkeys, int *off, hipStream_t st) {
+hipError_t launch_tile_offsets(const int *key, long long n, int nkeys, int shift, int *off,
+                              hipStream_t st) {
     hipLaunchKernelGGL(k_tile_offsets, dim3(blocks_for(n + 1, 256)), dim3(256), 0, st, key, n,
-                       nkeys, off);
+                       nkeys, shift, off);
+    return hipGetLastError();
+}
+
+hipError_t quads_first(const int *key, const int *perm_in, long long n, int shift,
+                       const int *tile_off, int *work, int *work2, int *perm_out, int *totals,
+                       int *scan_scratch, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    const unsigned nb = blocks_for(n, 256);
+    int *heads = work;              // n: heads, then their exclusive scan
+    int *starts = perm_out;         // n: run starts (perm_out is written last)
+    int *flag = work2, *fexcl = work2 + n;
+    hipLaunchKernelGGL(k_run_heads, dim3(nb), dim3(256), 0, st, key, n, heads);
+    hipError_t e = scan_exclusive(heads, heads, n, totals, scan_scratch, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_run_starts, dim3(nb), dim3(256), 0, st, key, n, (const int *)heads, starts);
+    hipLaunchKernelGGL(k_quad_flags, dim3(nb), dim3(256), 0, st, key, n, (const int *)heads,
+                       (const int *)starts, (const int *)totals, flag);
+    e = scan_exclusive(flag, fexcl, n, totals + 1, scan_scratch, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_quad_scatter, dim3(nb), dim3(256), 0, st, key, n, shift, tile_off,
+                       (const int *)flag, (const int *)fexcl, (const int *)(totals + 1), perm_in,
+                       perm_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_shift_copy(const int *src, int *dst, long long n, int shift, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_shift_copy, dim3(blocks_for(n, 256)), dim3(256), 0, st, src, dst, n, shift);
     return hipGetLastError();
 }
 
@@ -452,15 +577,15 @@ hipError_t launch_copy8(const void *src, void *dst, long long n, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_items(const DevSpecies *spt, const int *prefix, int nsp, int nslots, int chunk,
-                        int *counts, int *starts, int *scan_scratch, Item *items, int *nitems,
-                        int *queue, hipStream_t st) {
-    hipLaunchKernelGGL(k_item_count, dim3(blocks_for(nslots, 256)), dim3(256), 0, st, spt, prefix,
-                       nsp, nslots, chunk, counts);
+hipError_t launch_items(const DevSpecies *spt, const int *bprefix, int nb, const int *box_sp_off,
+                        const int *box_sp, int nslots, int chunk, int *counts, int *starts,
+                        int *scan_scratch, Item *items, int *nitems, int *queue, hipStream_t st) {
+    hipLaunchKernelGGL(k_item_count, dim3(blocks_for(nslots, 256)), dim3(256), 0, st, spt, bprefix,
+                       nb, box_sp_off, box_sp, nslots, chunk, counts);
     hipError_t e = scan_exclusive(counts, starts, nslots, nitems, scan_scratch, st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_item_fill, dim3(blocks_for(nslots, 256)), dim3(256), 0, st, spt, prefix,
-                       nsp, nslots, chunk, (const int *)starts, items);
+    hipLaunchKernelGGL(k_item_fill, dim3(blocks_for(nslots, 256)), dim3(256), 0, st, spt, bprefix,
+                       nb, box_sp_off, box_sp, nslots, chunk, (const int *)starts, items);
     hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, st, queue, 0);
     return hipGetLastError();
 }

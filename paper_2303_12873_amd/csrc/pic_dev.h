@@ -51,7 +51,10 @@ struct DevFields {
     double *J[3];
 };
 
-// Work item of the batched kernel: species, tile, first and last particle.
+// Work item of the batched kernel.  s >= 0: particles [p0, p1) of species s
+// in tile t.  s < 0: every particle of every species of box -1 - s in tile t
+// (p0, p1 unused), one field stage and one current flush for all of them.
+// t < 0 marks the end of the queue.
 struct Item {
     int s, t, p0, p1;
 };
@@ -75,6 +78,9 @@ struct KParams {
     int margin;               // cells staged around each tile (0 or 1)
     int jrow;                 // minimum row length of the LDS current tile
     int *strag_count;         // per species: entries in its straggler list
+    // species of each box (CSR: box_sp[box_sp_off[b] .. box_sp_off[b+1]))
+    const int *box_sp_off;
+    const int *box_sp;
 };
 
 }  // namespace pic

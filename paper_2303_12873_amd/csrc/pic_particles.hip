@@ -696,8 +696,9 @@ template <typename T> __device__ inline T quad_reduce_scatter(const T v[4]) {
 __device__ inline bool wave_any(bool p) { return __ballot(p) != 0ull; }
 
 // Esirkepov deposit into the LDS current tile with every lane active.
-// QUAD: lanes whose quad shares one window pool values and the quad's
-// first lane adds the sum; other lanes add their own non-zero values.
+// QUAD: a quad whose four lanes share one window pools each line: lane r
+// adds the quad's sum of edge r.  Other quads add their own non-zero values,
+// each lane starting at a different edge.
 template <int DIM, bool QUAD, typename R, class JA>
 __device__ __forceinline__ void deposit_converged(const JA &ja, const int c0[3], const R f0[3],
                                                   const int c1[3], const R f1[3], const R cq[3],
@@ -746,11 +747,16 @@ __device__ __forceinline__ void deposit_converged(const JA &ja, const int c0[3],
             const R sc = quad_reduce_scatter(v);
             const int r = threadIdx.x & 3;
             if (pool) {
-                if (r < ne && sc != R(0)) unsafeAtomicAdd(base + r * stride, (A)sc);
+                if (r < ne) unsafeAtomicAdd(base + r * stride, (A)sc);
             } else {
+                // Lane r of the quad adds edge (e + r) mod 4 at step e: lanes
+                // of one quad that share a cell never hit one address at once.
 #pragma unroll
-                for (int e = 0; e < K - 1; ++e)
-                    if (e < ne && v[e] != R(0)) unsafeAtomicAdd(base + e * stride, (A)v[e]);
+                for (int e = 0; e < 4; ++e) {
+                    const int ed = (e + r) & 3;
+                    const R x = ed == 0 ? v[0] : ed == 1 ? v[1] : ed == 2 ? v[2] : v[3];
+                    if (ed < ne && x != R(0)) unsafeAtomicAdd(base + ed * stride, (A)x);
+                }
             }
         } else {
 #pragma unroll
@@ -978,6 +984,10 @@ __global__ void __launch_bounds__(256) k_strag(KParams prm) {
 
 // ------------------------------------------------------------ tiled / batched
 
+__device__ inline int item_box(const KParams &prm, const Item &it) {
+    return it.s >= 0 ? prm.species[it.s].box : -1 - it.s;
+}
+
 // Walks the flattened (component, k, j, i) index of an LDS region, i
 // fastest, from `start` in steps of `stride`, with the coordinates updated
 // by carries instead of a division per element.
@@ -1003,12 +1013,57 @@ struct RegionWalk {
     }
 };
 
+// The particles [p0, p1) of species s in the current tile: lane -> particle
+// map: slot k takes particle (k mod G) * S + k / G of the range (S = lane
+// stride, G = ceil(n / S)), so that with S equal to the particles per cell
+// the lanes of one wave sit in distinct cells and their LDS atomics do not
+// collide on one address.  S = 1 is the identity.
+template <int DIM, class P, int MODE, bool QUAD>
+__device__ __forceinline__ void process_range(const KParams &prm, const DevBox &b, int s, int p0,
+                                              int p1, const Tile &tile,
+                                              const LdsField<typename P::FieldT> &lf,
+                                              const LdsJ<typename P::Acc> &lj) {
+    const DevSpecies &sp = prm.species[s];
+    const int tid = threadIdx.x, bs = blockDim.x;
+    const int n = p1 - p0;
+    if (n <= 0) return;
+    const int S = prm.lane_stride > 1 ? prm.lane_stride : 1;
+    const int G = (n + S - 1) / S;
+    const int total = G * S;
+    int q = tid / G, r = tid - (tid / G) * G;
+    const int dq = bs / G, dr = bs - (bs / G) * G;
+    if constexpr (MODE == MODE_FUSED) {
+        // every lane runs the same number of slots (the converged path)
+        const int rounds = (total + bs - 1) / bs;
+        for (int rd = 0; rd < rounds; ++rd) {
+            const int sl = tid + rd * bs;
+            const int idx = r * S + q;
+            const bool have = sl < total && idx < n;
+            particle_converged<DIM, P, QUAD>(b, sp, (long long)(p0 + (have ? idx : 0)), have, tile,
+                                             lf, lj, prm.err, prm.strag_count + s);
+            r += dr;
+            q += dq;
+            if (r >= G) { r -= G; q += 1; }
+        }
+    } else {
+        for (int sl = tid; sl < total; sl += bs) {
+            const int idx = r * S + q;
+            if (idx < n)
+                particle<DIM, P, MODE, true>(b, sp, (long long)(p0 + idx), prm.f, &tile, &lf, &lj,
+                                             prm.err, prm.strag_count + s);
+            r += dr;
+            q += dq;
+            if (r >= G) { r -= G; q += 1; }
+        }
+    }
+}
+
 template <int DIM, class P, int MODE, bool QUAD>
 __device__ __forceinline__ void process_item(const KParams &prm, const Item &it, char *smem) {
     using FT = typename P::FieldT;
     using A = typename P::Acc;
-    const DevSpecies &sp = prm.species[it.s];
-    const DevBox &b = prm.boxes[sp.box];
+    const int box = item_box(prm, it);
+    const DevBox &b = prm.boxes[box];
     Tile tile;
     {
         int t = it.t;
@@ -1065,45 +1120,13 @@ __device__ __forceinline__ void process_item(const KParams &prm, const Item &it,
         for (int idx = tid; idx < n; idx += bs) lj.base[idx] = A(0);
     }
     __syncthreads();
-    // Lane -> particle map: slot s takes particle (s mod G) * S + s / G of
-    // the item (S = lane stride, G = ceil(n / S)), so that with S equal to
-    // the particles per cell the lanes of one wave sit in distinct cells and
-    // their LDS atomics do not collide on one address.  S = 1 is the
-    // identity.
-    if constexpr (MODE == MODE_FUSED) {
-        // every lane runs the same number of slots (the converged path)
-        const int n = it.p1 - it.p0;
-        const int S = prm.lane_stride > 1 ? prm.lane_stride : 1;
-        const int G = (n + S - 1) / S;
-        const int total = G * S;
-        const int rounds = (total + bs - 1) / bs;
-        int q = tid / G, r = tid - (tid / G) * G;
-        const int dq = bs / G, dr = bs - (bs / G) * G;
-        for (int rd = 0; rd < rounds; ++rd) {
-            const int sl = tid + rd * bs;
-            const int idx = r * S + q;
-            const bool have = sl < total && idx < n;
-            particle_converged<DIM, P, QUAD>(b, sp, (long long)(it.p0 + (have ? idx : 0)), have, tile,
-                                             lf, lj, prm.err, prm.strag_count + it.s);
-            r += dr;
-            q += dq;
-            if (r >= G) { r -= G; q += 1; }
-        }
+    if (it.s >= 0) {
+        process_range<DIM, P, MODE, QUAD>(prm, b, it.s, it.p0, it.p1, tile, lf, lj);
     } else {
-        const int n = it.p1 - it.p0;
-        const int S = prm.lane_stride > 1 ? prm.lane_stride : 1;
-        const int G = (n + S - 1) / S;
-        const int total = G * S;
-        int q = tid / G, r = tid - (tid / G) * G;
-        const int dq = bs / G, dr = bs - (bs / G) * G;
-        for (int sl = tid; sl < total; sl += bs) {
-            const int idx = r * S + q;
-            if (idx < n)
-                particle<DIM, P, MODE, true>(b, sp, (long long)(it.p0 + idx), prm.f, &tile, &lf, &lj,
-                                             prm.err, prm.strag_count + it.s);
-            r += dr;
-            q += dq;
-            if (r >= G) { r -= G; q += 1; }
+        for (int k = prm.box_sp_off[box]; k < prm.box_sp_off[box + 1]; ++k) {
+            const int s = prm.box_sp[k];
+            const int *off = prm.species[s].tile_off;
+            process_range<DIM, P, MODE, QUAD>(prm, b, s, off[it.t], off[it.t + 1], tile, lf, lj);
         }
     }
     __syncthreads();
@@ -1134,12 +1157,12 @@ __global__ void __launch_bounds__(P::MAX_BLOCK) k_tiled(KParams prm) {
         if (PERSISTENT) {
             if (threadIdx.x == 0) {
                 int idx = atomicAdd(prm.queue, 1);
-                cur = idx < *prm.nitems ? prm.items[idx] : Item{-1, 0, 0, 0};
+                cur = idx < *prm.nitems ? prm.items[idx] : Item{0, -1, 0, 0};
             }
             __syncthreads();
             it = cur;
             __syncthreads();
-            if (it.s < 0) return;
+            if (it.t < 0) return;
         } else {
             if (round > 0) return;
             const int bidx = blockIdx.x;
@@ -1155,7 +1178,7 @@ __global__ void __launch_bounds__(P::MAX_BLOCK) k_tiled(KParams prm) {
         } else if constexpr (DIMS == 2) {
             process_item<2, P, MODE, QUAD>(prm, it, smem);
         } else {
-            const DevBox &b = prm.boxes[prm.species[it.s].box];
+            const DevBox &b = prm.boxes[item_box(prm, it)];
             if (b.dim == 3) process_item<3, P, MODE, QUAD>(prm, it, smem);
             else process_item<2, P, MODE, QUAD>(prm, it, smem);
         }

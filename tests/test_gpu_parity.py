@@ -138,9 +138,31 @@ def test_split_calls_equal_fused(prec, kernel):
 
 # ------------------------------------------------------------------ sort
 
+def _key_bits(n):
+    b = 0
+    while (1 << b) < n:
+        b += 1
+    return max(b, 1)
+
+
+def _oracle_sort(box, ref, cell_order):
+    """Oracle permutation, per-particle tile ids and tile offsets of the GPU
+    sort with or without the within-tile cell order."""
+    key = oracle.tile_keys(_grid(box), box.tile, ref) if ref.x.shape[1] else np.zeros(0, np.int32)
+    perm_o, count_o, off_o = oracle.stable_sort(key, box.ntiles)
+    if cell_order:
+        vol = box.tile[0] * (box.tile[1] if box.dim == 3 else 1) * box.tile[2]
+        cb = _key_bits(vol)
+        assert _key_bits(box.ntiles + 1) + cb + 2 <= 31
+        ck = oracle.cell_order_keys(_grid(box), box.tile, cb, ref) if ref.x.shape[1] else np.zeros(0, np.int64)
+        perm_o = oracle.quad_order(ck, cb) if cell_order == 2 else oracle.stable_perm(ck)
+    return perm_o, key, off_o
+
+
 @pytest.mark.parametrize("case", ["random", "one_tile", "sparse", "ragged2d", "empty"])
 @pytest.mark.parametrize("prec", (pic.PIC_FP64, pic.PIC_FP32_SPLIT))
-def test_sort_bit_exact(case, prec):
+@pytest.mark.parametrize("cell_order", (-1, 1, 2))
+def test_sort_bit_exact(case, prec, cell_order):
     seeds = {"random": 1, "one_tile": 2, "sparse": 3, "ragged2d": 4, "empty": 5}
     rng = np.random.default_rng(seeds[case])
     dim = 2 if case == "ragged2d" else 3
@@ -163,9 +185,8 @@ def test_sort_bit_exact(case, prec):
     wl.species = [p]
     box = wl.boxes[0]
     ref = p.numpy()
-    key = oracle.tile_keys(_grid(box), box.tile, ref) if p.np else np.zeros(0, np.int32)
-    perm_o, count_o, off_o = oracle.stable_sort(key, box.ntiles)
-    run = GpuRun(wl, prec)
+    perm_o, key, off_o = _oracle_sort(box, ref, max(cell_order, 0))
+    run = GpuRun(wl, prec, cell_order=cell_order)
     perm = torch.full((max(p.np, 1),), -1, dtype=torch.int32, device="cuda")[:p.np]
     keys = torch.full((max(p.np, 1),), -1, dtype=torch.int32, device="cuda")[:p.np]
     offs = torch.full((box.ntiles + 1,), -1, dtype=torch.int32, device="cuda")
@@ -181,8 +202,10 @@ def test_sort_bit_exact(case, prec):
     run.free()
 
 
-def test_sort_large_multi_pass():
-    """~2 M particles, 2^15+ tiles: three radix passes, many sort blocks."""
+@pytest.mark.parametrize("cell_order", (-1, 1, 2))
+def test_sort_large_multi_pass(cell_order):
+    """~2 M particles, 2^15 tiles: two radix passes (tile id) or three (with
+    the cell order), many sort blocks."""
     box = pi.Box(3, (256, 128, 64), pi.DT3, 1, (4, 4, 4))
     g = torch.Generator().manual_seed(5)
     npart = 2_000_003
@@ -191,9 +214,8 @@ def test_sort_large_multi_pass():
     wl = pi.Workload("sortbig", [box], [p], [torch.zeros(3, box.ncells, dtype=torch.float64)],
                      [torch.zeros(3, box.ncells, dtype=torch.float64)])
     ref = p.numpy()
-    key = oracle.tile_keys(_grid(box), box.tile, ref)
-    perm_o, _, off_o = oracle.stable_sort(key, box.ntiles)
-    run = GpuRun(wl, pic.PIC_FP32_SPLIT)
+    perm_o, _, off_o = _oracle_sort(box, ref, max(cell_order, 0))
+    run = GpuRun(wl, pic.PIC_FP32_SPLIT, cell_order=cell_order)
     perm = torch.empty(npart, dtype=torch.int32, device="cuda")
     offs = torch.empty(box.ntiles + 1, dtype=torch.int32, device="cuda")
     pic.pic_sort_tiles(run.ctx, run.sp, perm_out=[perm], tile_offset_out=[offs])
@@ -354,4 +376,26 @@ def test_lane_stride_margin_and_stale_sort(prec, tol, kernel, stride):
     assert rel_l2(J, Jo) <= tol and rel_l2(E, Eo) <= tol, (rel_l2(J, Jo), rel_l2(E, Eo))
     x, u = run.state_np()
     assert rel_l2(u, sps[0].u) <= tol
+    run.free()
+
+
+@pytest.mark.parametrize("prec,tol", ((pic.PIC_FP64, TOL64), (pic.PIC_FP32_SPLIT, TOL32)))
+@pytest.mark.parametrize("chunk,cell_order", ((4096, 2), (4096, 1), (4096, -1), (45, 2)))
+def test_two_species_merged_items(prec, tol, chunk, cell_order):
+    """Electrons and ions in one box, quad-pooled deposit (lane stride 1):
+    with a large chunk every box tile is one work item over both species;
+    with a small one tiles split into per-species chunks.  Warm plasma and a
+    single sort, so quads lose their shared cell while the steps run."""
+    wl = pi.uniform_box((16, 16, 16), 4, 0.05, 0.3, 3, 1700, "cpu", tile=(8, 8, 8),
+                        fields="fourier", species=("e", "i"))
+    Eo, Bo, Jo, sps = _oracle_steps(wl, 4)
+    run = GpuRun(wl, prec, kernel=pic.PIC_KERNEL_BATCHED, chunk=chunk, lane_stride=1,
+                 cell_order=cell_order, block=256)
+    run.sort()
+    for _ in range(4):
+        run.particles()
+        pic.pic_fdtd_step(run.ctx, run.f)
+    run.check()
+    E, B, J = run.fields_np()
+    assert rel_l2(J, Jo) <= tol and rel_l2(E, Eo) <= tol, (rel_l2(J, Jo), rel_l2(E, Eo))
     run.free()

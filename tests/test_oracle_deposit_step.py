@@ -240,3 +240,114 @@ def test_stable_sort_and_keys():
     assert list(perm) == ref
     assert offset[-1] == len(key) and (np.diff(offset) == count).all()
     assert np.array_equal(count, np.bincount(key, minlength=len(count)))
+
+
+def _cells_in_tile(sp, box):
+    c = np.floor(sp.x).astype(np.int64) % np.array(box.n)[:, None]
+    t = np.array(box.tile)[:, None]
+    return c // t, c % t
+
+
+def test_cell_order_keys():
+    """The within-tile cell order: its tile part is the tile id, equal keys
+    mean equal cells (so a stable sort makes each cell's particles
+    contiguous), and two different cells of one class that share a row along
+    an axis differ by a multiple of 4 along it (the layout's promise that
+    consecutive cells never deposit onto one LDS node)."""
+    from pic_inputs import uniform_box
+    wl = uniform_box((16, 12, 9), 3, 0.01, 0.3, 1, 79, "cpu", tile=(8, 4, 8))
+    box = wl.boxes[0]
+    sp = wl.species[0].numpy()
+    g = oracle.make_grid(3, box.n, box.dx, box.dt, 1)
+    cbits = 8                                   # 8 * 4 * 8 = 256 cells per tile
+    key = oracle.cell_order_keys(g, box.tile, cbits, sp)
+    assert np.array_equal(key >> (cbits + 2), oracle.tile_keys(g, box.tile, sp))
+    tiles, local = _cells_in_tile(sp, box)
+    cell = np.floor(sp.x).astype(np.int64)
+    ids = {}
+    for p in range(key.shape[0]):
+        ids.setdefault(int(key[p]), set()).add(tuple(cell[:, p]))
+    assert all(len(v) == 1 for v in ids.values())
+    assert len(ids) == len({tuple(cell[:, p]) for p in range(key.shape[0])})
+    cls = (key >> cbits) & 3
+    n = key.shape[0]
+    for p in range(0, n, 5):
+        same = (key >> (cbits + 2) == key[p] >> (cbits + 2)) & (cls == cls[p]) & (key != key[p])
+        for d in range(3):
+            o = [e for e in range(3) if e != d]
+            row = same & (local[o[0]] == local[o[0], p]) & (local[o[1]] == local[o[1], p])
+            dd = np.abs(local[d, row] - local[d, p])
+            assert (dd % 4 == 0).all() and (dd >= 4).all()
+    perm = oracle.stable_perm(key)
+    assert list(perm) == sorted(range(n), key=lambda i: (key[i], i))
+    k = key[perm]
+    change = np.nonzero(np.diff(k))[0]
+    seen = set()
+    for run in np.split(np.arange(n), change + 1):
+        c = tuple(cell[:, perm[run[0]]])
+        assert c not in seen
+        seen.add(c)
+
+
+def test_cell_order_keys_2d_brute():
+    """2D: every cell of a 8x8 box with 4x4 tiles, one particle each; keys
+    enumerate (tile, class, cell) exactly, checked cell by cell."""
+    n = (8, 1, 8)
+    xs, zs = np.meshgrid(np.arange(8) + 0.5, np.arange(8) + 0.5, indexing="ij")
+    x = np.zeros((3, 64))
+    x[0] = xs.ravel()
+    x[2] = zs.ravel()
+    sp = _sp(x, np.zeros((3, 64)), np.ones(64))
+    g = oracle.make_grid(2, n, (1.0, 1.0, 1.0), 0.5, 1)
+    key = oracle.cell_order_keys(g, (4, 1, 4), 4, sp)
+    for p in range(64):
+        cx, cz = int(x[0, p]), int(x[2, p])
+        tile = cx // 4 + 2 * (cz // 4)
+        lx, lz = cx % 4, cz % 4
+        assert key[p] >> 6 == tile
+        assert (key[p] >> 4) & 3 == (lx + lz) % 4
+        assert key[p] & 15 == lx + 4 * lz
+    assert len(set(key.tolist())) == 64
+
+
+def test_quad_order():
+    """Whole groups of four first: the result is a permutation that keeps
+    the tile grouping of the cell order; inside each tile every aligned group
+    of four of the first part shares one cell, the second part holds fewer
+    than four particles of any cell, and each part keeps the cell order
+    (checked against the stable cell-order permutation)."""
+    from pic_inputs import uniform_box
+    wl = uniform_box((16, 8, 8), 4, 0.01, 0.3, 1, 81, "cpu", tile=(8, 8, 8))
+    box = wl.boxes[0]
+    sp = wl.species[0].numpy()
+    rng = np.random.default_rng(11)
+    keep = np.sort(rng.choice(sp.x.shape[1], size=sp.x.shape[1] * 3 // 4, replace=False))
+    x = sp.x[:, keep] + rng.uniform(-0.45, 0.45, size=(3, keep.size))   # drifted cells
+    x = np.mod(x, np.array(box.n, float)[:, None])
+    sp = _sp(x, sp.u[:, keep], sp.w[keep])
+    g = oracle.make_grid(3, box.n, box.dx, box.dt, 1)
+    cbits = 9
+    key = oracle.cell_order_keys(g, box.tile, cbits, sp)
+    base = oracle.stable_perm(key)
+    perm = oracle.quad_order(key, cbits)
+    n = key.shape[0]
+    assert sorted(perm.tolist()) == list(range(n))
+    tiles = key >> (cbits + 2)
+    assert np.array_equal(tiles[perm], tiles[base])
+    rank_in_base = np.empty(n, np.int64)
+    rank_in_base[base] = np.arange(n)
+    for t in np.unique(tiles):
+        seg = perm[tiles[perm] == t]
+        counts = {}
+        for i in seg:
+            counts[key[i]] = counts.get(key[i], 0) + 1
+        whole = sum(c - c % 4 for c in counts.values())
+        first, second = seg[:whole], seg[whole:]
+        for q in range(0, whole, 4):
+            assert len(set(key[first[q:q + 4]].tolist())) == 1
+        rest = {}
+        for i in second:
+            rest[key[i]] = rest.get(key[i], 0) + 1
+        assert all(v < 4 and v == counts[k] % 4 for k, v in rest.items())
+        assert (np.diff(rank_in_base[first]) > 0).all()
+        assert (np.diff(rank_in_base[second]) > 0).all()
