@@ -118,6 +118,13 @@ typedef struct {
                             pooling of the deposit at lane_stride 1).  1 and
                             2 apply when tile id and cell fit a 31-bit key.
                             0 = default: 2 for BATCHED, else -1. */
+    int32_t quad_spread; /* TILED/BATCHED at lane_stride 1: 1 = the 16 quads
+                            of a wave are taken ceil(nquads/16) quads apart
+                            in a species' tile range instead of in a row, so
+                            cells holding several quads of particles spread
+                            over waves; -1 = in a row; 0 = default: 1 for a
+                            species with at least 6 particles per cell of its
+                            box on average, else -1. */
 } pic_tuning;
 
 typedef struct {

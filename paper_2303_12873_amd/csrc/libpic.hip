@@ -278,6 +278,8 @@ pic_status bind_species(pic_ctx *c, const pic_species *sp, int nsp, bool need_pu
         d.carry = sl.carry;
         d.strag = sl.strag;
         d.tile_off = sl.tile_off;
+        d.spread = c->tun.quad_spread > 0 ||
+                   (c->tun.quad_spread == 0 && p.np >= 6 * c->hbox[p.box].ncells);
         prefix[s + 1] = prefix[s] + b.ntiles;
     }
     (void)realloc_happened;
@@ -609,6 +611,7 @@ pic_status pic_init(pic_ctx **out, const pic_box_desc *boxes, int32_t nboxes, pi
     t.lane_stride = 1;
     t.pad = 0;
     t.cell_order = 0;
+    t.quad_spread = 0;
     if (tuning) {
         t.kernel = tuning->kernel;
         if (tuning->block) t.block = tuning->block;
@@ -617,6 +620,7 @@ pic_status pic_init(pic_ctx **out, const pic_box_desc *boxes, int32_t nboxes, pi
         if (tuning->lane_stride) t.lane_stride = tuning->lane_stride;
         t.pad = tuning->pad;
         t.cell_order = tuning->cell_order;
+        t.quad_spread = tuning->quad_spread;
     }
     if (t.kernel < 0 || t.kernel > 2) return fail(PIC_ERR_ARG, "bad kernel form");
     const int max_block = prec == PIC_FP64 ? 512 : 1024;

@@ -43,6 +43,9 @@ struct DevSpecies {
     // exclusive per-tile offsets from the last sort, ntiles+2 entries
     // (the extra bucket holds particles with invalid positions)
     int *tile_off;
+    int spread;         // tiled kernels at lane stride 1: a wave's 16 quads
+                        // are taken ceil(nquads/16) quads apart, not in a
+                        // row (several quads per cell)
 };
 
 struct DevFields {

@@ -749,11 +749,14 @@ __device__ __forceinline__ void deposit_converged(const JA &ja, const int c0[3],
             if (pool) {
                 if (r < ne) unsafeAtomicAdd(base + r * stride, (A)sc);
             } else {
-                // Lane r of the quad adds edge (e + r) mod 4 at step e: lanes
-                // of one quad that share a cell never hit one address at once.
+                // Lane r of the quad adds edge (e + r) mod NE at step e, NE =
+                // K - 1 edges per line: for NE = 4 lanes of one quad that
+                // share a cell never hit one address at once (NE < 4: at
+                // most lanes r and r + NE do).
+                constexpr int NE = K - 1;
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int ed = (e + r) & 3;
+                for (int e = 0; e < NE; ++e) {
+                    const int ed = (e + r) % NE;
                     const R x = ed == 0 ? v[0] : ed == 1 ? v[1] : ed == 2 ? v[2] : v[3];
                     if (ed < ne && x != R(0)) unsafeAtomicAdd(base + ed * stride, (A)x);
                 }
@@ -1033,6 +1036,24 @@ __device__ __forceinline__ void process_range(const KParams &prm, const DevBox &
     int q = tid / G, r = tid - (tid / G) * G;
     const int dq = bs / G, dr = bs - (bs / G) * G;
     if constexpr (MODE == MODE_FUSED) {
+        if (QUAD && sp.spread) {
+            // Quad slot qs of the range takes quad (qs mod 16) * C + qs / 16
+            // (C = ceil(nquads / 16)): the 16 quads of a wave lie C quads
+            // apart, so cells holding several whole quads do not fill a
+            // wave with one cell's stencil.
+            const int C = (((n + 3) >> 2) + 15) >> 4;
+            const int tot = C * 64;
+            const int rounds = (tot + bs - 1) / bs;
+            for (int rd = 0; rd < rounds; ++rd) {
+                const int sl = tid + rd * bs;
+                const int qs = sl >> 2;
+                const int idx = (((qs & 15) * C + (qs >> 4)) << 2) + (sl & 3);
+                const bool have = sl < tot && idx < n;
+                particle_converged<DIM, P, QUAD>(b, sp, (long long)(p0 + (have ? idx : 0)), have,
+                                                 tile, lf, lj, prm.err, prm.strag_count + s);
+            }
+            return;
+        }
         // every lane runs the same number of slots (the converged path)
         const int rounds = (total + bs - 1) / bs;
         for (int rd = 0; rd < rounds; ++rd) {

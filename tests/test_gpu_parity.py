@@ -380,8 +380,9 @@ def test_lane_stride_margin_and_stale_sort(prec, tol, kernel, stride):
 
 
 @pytest.mark.parametrize("prec,tol", ((pic.PIC_FP64, TOL64), (pic.PIC_FP32_SPLIT, TOL32)))
-@pytest.mark.parametrize("chunk,cell_order", ((4096, 2), (4096, 1), (4096, -1), (45, 2)))
-def test_two_species_merged_items(prec, tol, chunk, cell_order):
+@pytest.mark.parametrize("chunk,cell_order,spread", ((4096, 2, 0), (4096, 1, 0), (4096, -1, 0),
+                                                   (45, 2, 0), (4096, 2, 1), (45, 2, 1)))
+def test_two_species_merged_items(prec, tol, chunk, cell_order, spread):
     """Electrons and ions in one box, quad-pooled deposit (lane stride 1):
     with a large chunk every box tile is one work item over both species;
     with a small one tiles split into per-species chunks.  Warm plasma and a
@@ -390,7 +391,7 @@ def test_two_species_merged_items(prec, tol, chunk, cell_order):
                         fields="fourier", species=("e", "i"))
     Eo, Bo, Jo, sps = _oracle_steps(wl, 4)
     run = GpuRun(wl, prec, kernel=pic.PIC_KERNEL_BATCHED, chunk=chunk, lane_stride=1,
-                 cell_order=cell_order, block=256)
+                 cell_order=cell_order, block=256, quad_spread=spread)
     run.sort()
     for _ in range(4):
         run.particles()
