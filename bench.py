@@ -26,15 +26,54 @@ if ROOT not in sys.path:
 
 METRIC = "particle-steps/s (gather+push+deposit), FP32+batched vs FP64 plain, 1 GPU"
 
-# Algorithmic work per unit (the design doc derives them): bytes a particle must
-# move per step (read x,u,w; write x,u), bytes per cell of E/B read and J
-# written by the particle kernel, and flops per particle (FMA = 2) by order.
+# Algorithmic work per unit: bytes a particle must move per step (read
+# position, u, w; write position, u), bytes per cell of E/B read and J
+# written by the particle kernel, and flops per particle (FMA = 2) by shape
+# order (gather 12 (n+1)^3, push ~100, Esirkepov deposit).
 BYTES_PER_PARTICLE = {"fp64": 104, "fp32": 60, "fp32_2d": 52}
 BYTES_PER_CELL = {"fp64": 72, "fp32": 48}
 FLOPS_PER_PARTICLE = {1: 550, 2: 1150, 3: 2150}
 PEAK_HBM_GBS = 8000.0
-PEAK_FP32_TFLOPS = 157.3
-PEAK_FP64_TFLOPS = 78.6
+# Vector ALU peak the kernels can reach: 256 CUs x 4 SIMDs x 16 lanes x 2
+# flops (FMA) x 2.4 GHz = 78.6 TFLOP/s for FP32 without packed-FP32
+# instructions (the kernels are built without them) and for FP64.
+PEAK_VALU_TFLOPS = 78.6
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_tiled_split_c5_traffic.md")
+KERNEL_SOURCES = ("pic_particles.hip", "pic_math.h", "pic_dev.h")
+
+
+def kernel_source_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for n in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2303_12873_amd", "csrc", n), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def launch_config(tile, block, stride, cell_order):
+    return f"tile={tuple(tile)} block={block} lane_stride={stride} cell_order={cell_order}"
+
+
+def measured_traffic(workload, config):
+    """HBM bytes per launch of the particle kernel from the committed
+    rocprofv3 counter summary, if it was taken on this workload and launch
+    configuration with the current kernel sources; else None."""
+    if not os.path.exists(TRAFFIC_SUMMARY):
+        return None
+    fields = {}
+    with open(TRAFFIC_SUMMARY) as f:
+        for line in f:
+            if ":" in line and line.startswith("- "):
+                k, v = line[2:].split(":", 1)
+                fields[k.strip()] = v.strip().strip("`")
+    if (fields.get("workload") != workload or fields.get("config") != config
+            or fields.get("kernel_source_sha256") != kernel_source_sha()):
+        return None
+    try:
+        return int(fields["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def log(*a):
@@ -56,7 +95,8 @@ def build_workload(name, device):
     raise SystemExit(f"unknown workload {name}")
 
 
-def run_form(wl, precision, kernel, steps, warmup, sort_every, tile, block, chunk, wg, stride):
+def run_form(wl, precision, kernel, steps, warmup, sort_every, tile, block, chunk, wg, stride,
+             cell_order=0):
     import torch
     import paper_2303_12873_amd as pic
     import pic_inputs as pi
@@ -66,11 +106,14 @@ def run_form(wl, precision, kernel, steps, warmup, sort_every, tile, block, chun
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         ctx = pic.pic_init(boxes, precision, stream=stream.cuda_stream, kernel=kernel,
-                           block=block, chunk=chunk, wg_per_cu=wg, lane_stride=stride)
+                           block=block, chunk=chunk, wg_per_cu=wg, lane_stride=stride,
+                           cell_order=cell_order)
         f = pic.make_fields(boxes, wl.E, wl.B, precision)
         sp = [pic.make_species(p, precision) for p in wl.species]
     torch.cuda.synchronize()
     np_tot = sum(s.np for s in sp)
+    # HIP events around the particle kernel inside every step's graph
+    pic.pic_set_timing(ctx, True)
 
     def one(k):
         pic.pic_step(ctx, f, sp, sort=(k % sort_every == 0))
@@ -84,26 +127,20 @@ def run_form(wl, precision, kernel, steps, warmup, sort_every, tile, block, chun
     ev1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     ev0.record(stream)
+    kms = []
     for k in range(steps):
         one(k)
+        kms.append(pic.pic_kernel_ms(ctx))     # waits for this step's kernel
     ev1.record(stream)
     torch.cuda.synchronize()
     ms_step = ev0.elapsed_time(ev1) / steps
+    ms_adv = sum(kms) / len(kms)
     pic.pic_check(ctx)
-    # The particle kernel alone (plus its J clear and queue reset): the
-    # dominant kernel for the roofline figures.
-    nrep = max(3, min(10, steps))
-    pic.pic_sort_tiles(ctx, sp)
+    pic.pic_set_timing(ctx, False)
+    # the sort alone, then the field update alone (breakdown)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
-    e0.record(stream)
-    for _ in range(nrep):
-        pic.pic_advance(ctx, f, sp)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms_adv = e0.elapsed_time(e1) / nrep
-    # and the sort alone
     e0.record(stream)
     pic.pic_sort_tiles(ctx, sp)
     e1.record(stream)
@@ -119,7 +156,7 @@ def run_form(wl, precision, kernel, steps, warmup, sort_every, tile, block, chun
     del f, sp
     torch.cuda.empty_cache()
     return dict(np=np_tot, ms_step=ms_step, ms_advance=ms_adv, ms_sort=ms_sort, ms_fdtd=ms_fdtd,
-                cells=sum(b.ncells for b in boxes))
+                cells=sum(b.ncells for b in boxes), kernel_ms_min=min(kms), kernel_ms_max=max(kms))
 
 
 def cpu_baseline(workload, order):
@@ -177,6 +214,11 @@ def main():
     ap.add_argument("--wg-per-cu", type=int, default=2)
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison form")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--cell-order", type=int, default=0,
+                    help="FP32 within-tile order without the tuner (-1, 1, 2; 0 = library default)")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip the autotuner (use --tile32/--block/--stride and the default order)")
+    ap.add_argument("--tune-budget", type=float, default=120.0, help="autotuner time budget (s)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -198,9 +240,28 @@ def main():
     log(f"workload {wl.name}: {wl.np_total} particles, "
         f"{sum(b.ncells for b in wl.boxes)} cells, generated in {time.time() - t0:.1f}s")
 
+    cell_order = args.cell_order
+    tuned = None
+    if not args.no_tune:
+        from paper_2303_12873_amd.autotune import tune
+        # Tune on the workload itself (a half-size sample ranked the
+        # candidates differently).  Each candidate runs its whole sort period
+        # (drift included); the picked sort interval is then used by both
+        # forms.
+        t1 = time.time()
+        best, table = tune(wl, pic.PIC_FP32_SPLIT, budget_s=args.tune_budget, cache=None, log=log)
+        torch.cuda.empty_cache()
+        if best is not None:
+            args.tile32, args.block, args.chunk = tuple(best.tile), best.block, best.chunk
+            args.wg_per_cu, args.stride, cell_order = best.wg_per_cu, best.lane_stride, best.cell_order
+            args.sort_every = best.sort_every
+            tuned = {"picked": best.key(), "candidates": len(table),
+                     "seconds": round(time.time() - t1, 1)}
+        log(f"  autotuner: {tuned}")
     log("FP32 split + batched form")
     r32 = run_form(wl, pic.PIC_FP32_SPLIT, pic.PIC_KERNEL_BATCHED, args.steps, args.warmup,
-                   args.sort_every, args.tile32, args.block, args.chunk, args.wg_per_cu, args.stride)
+                   args.sort_every, args.tile32, args.block, args.chunk, args.wg_per_cu, args.stride,
+                   cell_order)
     log(f"  {r32}")
     r64 = None
     if not args.no_fp64:
@@ -218,16 +279,20 @@ def main():
     t_adv = r32["ms_advance"] * 1e-3
     gbs = bytes_launch / t_adv / 1e9
     tfl = flops_launch / t_adv / 1e12
-    f_hbm, f_alu = gbs / PEAK_HBM_GBS, tfl / PEAK_FP32_TFLOPS
+    f_hbm, f_alu = gbs / PEAK_HBM_GBS, tfl / PEAK_VALU_TFLOPS
+    traffic = measured_traffic(wl.name, launch_config(args.tile32, args.block, args.stride,
+                                                       cell_order))
     if f_alu >= f_hbm:
-        roof = {"bound": "alu", "achieved": round(tfl, 3), "peak": PEAK_FP32_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(f_alu, 4), "traffic": None,
+        roof = {"bound": "alu", "achieved": round(tfl, 3), "peak": PEAK_VALU_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(f_alu, 4), "traffic": traffic,
                 "hbm_frac": round(f_hbm, 4), "hbm_achieved_GBs": round(gbs, 1)}
     else:
         roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": round(f_hbm, 4), "traffic": None, "alu_frac": round(f_alu, 4)}
-    roof["kernel"] = "k_tiled<Split, FUSED, persistent> (pic_advance)"
+                "frac": round(f_hbm, 4), "traffic": traffic, "alu_frac": round(f_alu, 4)}
+    roof["kernel"] = "k_tiled<Split, FUSED, persistent> (particle part of each step's graph)"
     roof["kernel_ms"] = round(r32["ms_advance"], 4)
+    roof["algorithmic_bytes_per_launch"] = bytes_launch
+    roof["algorithmic_flops_per_launch"] = flops_launch
 
     out = {
         "metric": METRIC, "value": value, "unit": "particle-steps/s", "n_gpus": 1,
@@ -237,7 +302,8 @@ def main():
         "config": {"workload": wl.name, "cells": ncells, "particles": r32["np"], "order": order,
                    "form": "fp32_split_batched_graph", "sort_every": args.sort_every,
                    "tile": list(args.tile32), "block": args.block, "chunk": args.chunk,
-                   "wg_per_cu": args.wg_per_cu, "lane_stride": args.stride},
+                   "wg_per_cu": args.wg_per_cu, "lane_stride": args.stride,
+                   "cell_order": cell_order, "autotuned": tuned},
         "roofline": roof,
         "breakdown_ms": {"advance": r32["ms_advance"], "sort": r32["ms_sort"],
                          "fdtd": r32["ms_fdtd"]},

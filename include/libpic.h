@@ -224,6 +224,19 @@ const char *pic_last_error(void);
 /* Number of workgroups the context's kernels fill the device with (CUs). */
 int32_t pic_device_cus(pic_ctx *ctx);
 
+/* Timing of the tiled particle kernel (TILED/BATCHED forms).  With on != 0
+ * every later launch of it -- by pic_advance, pic_gather_push,
+ * pic_deposit_J, or inside the graph of pic_step (graphs are recorded
+ * separately with and without timing) -- is bracketed by two one-thread
+ * kernels on the context's stream that store the device's constant-rate
+ * wall clock (HIP events recorded inside a graph give no elapsed time on
+ * this runtime).  pic_kernel_ms waits for the stream and returns in *ms the
+ * time between the two stamps of the most recent timed launch (the kernel
+ * plus two launch gaps of a few microseconds); PIC_ERR_STATE if none was
+ * recorded since pic_set_timing. */
+pic_status pic_set_timing(pic_ctx *ctx, int32_t on);
+pic_status pic_kernel_ms(pic_ctx *ctx, float *ms);
+
 #ifdef __cplusplus
 }
 #endif

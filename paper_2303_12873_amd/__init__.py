@@ -27,7 +27,8 @@ PIC_KERNEL_DIRECT, PIC_KERNEL_TILED, PIC_KERNEL_BATCHED = 0, 1, 2
 
 EXPORTED = ["pic_init", "pic_sort_tiles", "pic_gather_push", "pic_deposit_J", "pic_advance",
             "pic_fdtd_step", "pic_step", "pic_deposit_rho", "pic_div_edge", "pic_check",
-            "pic_free", "pic_status_str", "pic_last_error", "pic_device_cus"]
+            "pic_free", "pic_status_str", "pic_last_error", "pic_device_cus", "pic_set_timing",
+            "pic_kernel_ms"]
 
 
 class pic_box_desc(C.Structure):
@@ -83,6 +84,8 @@ def lib():
         L.pic_status_str.restype = C.c_char_p
         L.pic_last_error.restype = C.c_char_p
         L.pic_device_cus.argtypes = [P]
+        L.pic_set_timing.argtypes = [P, I]
+        L.pic_kernel_ms.argtypes = [P, C.POINTER(C.c_float)]
         for n in EXPORTED:
             if n not in ("pic_status_str", "pic_last_error", "pic_device_cus"):
                 getattr(L, n).restype = C.c_int
@@ -296,6 +299,16 @@ def pic_free(ctx):
 
 def pic_device_cus(ctx) -> int:
     return int(lib().pic_device_cus(ctx))
+
+
+def pic_set_timing(ctx, on: bool = True):
+    _check(lib().pic_set_timing(ctx, int(bool(on))))
+
+
+def pic_kernel_ms(ctx) -> float:
+    ms = C.c_float()
+    _check(lib().pic_kernel_ms(ctx, C.byref(ms)))
+    return float(ms.value)
 
 
 def pic_status_str(status: int) -> str:

@@ -1,5 +1,7 @@
-"""Autotuner of the batched particle kernel: tile edge, workgroup size,
-particles per work item and persistent workgroups per CU.
+"""Autotuner of the batched particle kernel: tile edge (hence the LDS
+budget), workgroup size, particles per work item, persistent workgroups per
+CU, lane stride (particles per wavefront slot pattern), the within-tile
+particle order of the sort and the sort interval.
 
 Every candidate runs the same inputs for a few whole steps through the C ABI
 (its own context, its own copy of the particles); candidates whose fields
@@ -30,17 +32,28 @@ class Candidate:
     block: int
     chunk: int
     wg_per_cu: int
+    lane_stride: int = 1
+    cell_order: int = 2
+    sort_every: int = 8
 
     def key(self):
-        return f"t{self.tile}-b{self.block}-c{self.chunk}-w{self.wg_per_cu}"
+        return (f"t{self.tile}-b{self.block}-c{self.chunk}-w{self.wg_per_cu}-s{self.lane_stride}"
+                f"-o{self.cell_order}-e{self.sort_every}")
 
 
-def default_space(dim3: bool):
-    tiles = [(4, 4, 4), (8, 8, 8), (8, 8, 4)] if dim3 else [(8, 1, 8), (16, 1, 16), (8, 1, 16)]
-    blocks = [128, 256, 512]
-    chunks = [1024, 4096]
-    wgs = [1, 2, 4]
-    return [Candidate(t, b, c, w) for t, b, c, w in itertools.product(tiles, blocks, chunks, wgs)]
+def default_space(dim3: bool, precision=pic.PIC_FP32_SPLIT, sort_every=(8, 16)):
+    """Tile edges whose LDS stage fits, the largest workgroup of the
+    precision (smaller ones were slower on every workload measured), lane
+    strides 1 (quad-pooled deposit) and 4 with the within-tile orders that
+    suit them, and sort intervals."""
+    tiles = [(8, 8, 8), (8, 8, 4)] if dim3 else [(8, 1, 8), (16, 1, 16)]
+    blocks = [1024] if precision == pic.PIC_FP32_SPLIT else [512]
+    out = []
+    for t, b, e in itertools.product(tiles, blocks, sort_every):
+        out.append(Candidate(t, b, 4096, 2, 1, 2, e))
+        out.append(Candidate(t, b, 4096, 2, 1, 1, e))
+        out.append(Candidate(t, b, 4096, 2, 4, -1, e))
+    return out
 
 
 def workload_key(wl, precision) -> str:
@@ -57,22 +70,27 @@ def _retile(boxes, tile):
                    tuple(tile) if b.dim == 3 else (tile[0], 1, tile[2]), b.dx) for b in boxes]
 
 
-def _run(wl, precision, cand: Candidate, steps: int, sort_every: int, stream):
+def _run(wl, precision, cand: Candidate, steps: int, stream, warm: int = 4):
     boxes = _retile(wl.boxes, cand.tile)
     with torch.cuda.stream(stream):
         ctx = pic.pic_init(boxes, precision, stream=stream.cuda_stream,
                            kernel=pic.PIC_KERNEL_BATCHED, block=cand.block, chunk=cand.chunk,
-                           wg_per_cu=cand.wg_per_cu)
+                           wg_per_cu=cand.wg_per_cu, lane_stride=cand.lane_stride,
+                           cell_order=cand.cell_order)
         f = pic.make_fields(boxes, wl.E, wl.B, precision)
         sp = [pic.make_species(p, precision) for p in wl.species]
     try:
-        pic.pic_step(ctx, f, sp, sort=True)          # record + warm
+        # Warm steps first, so that the timed window's sorts reorder
+        # particles that have moved (the first sort of generated inputs
+        # leaves an unusually regular order behind it).
+        for k in range(warm):
+            pic.pic_step(ctx, f, sp, sort=(k == 0))
         torch.cuda.synchronize()
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record(stream)
         for k in range(steps):
-            pic.pic_step(ctx, f, sp, sort=((k + 1) % sort_every == 0))
+            pic.pic_step(ctx, f, sp, sort=(k % cand.sort_every == 0))
         e1.record(stream)
         torch.cuda.synchronize()
         pic.pic_check(ctx)
@@ -85,18 +103,23 @@ def _run(wl, precision, cand: Candidate, steps: int, sort_every: int, stream):
 
 
 def tune(wl, precision=pic.PIC_FP32_SPLIT, space: Optional[List[Candidate]] = None,
-         steps: int = 3, sort_every: int = 4, budget_s: float = 120.0,
+         steps: Optional[int] = None, budget_s: float = 120.0,
          cache: Optional[str] = DEFAULT_CACHE, log=print):
-    """Returns (best Candidate, table of (key, ms or reason))."""
+    """Returns (best Candidate, table of (key, ms or reason)).  Each candidate
+    runs `steps` whole steps (default: the longest sort interval of the
+    space, so every candidate's window holds its sort and the drift after
+    it) after four warm steps."""
     dim3 = all(b.dim == 3 for b in wl.boxes)
-    space = space or default_space(dim3)
+    space = space or default_space(dim3, precision)
+    steps = steps or max(c.sort_every for c in space)
     wkey = f"{torch.cuda.get_device_name(0)}|{workload_key(wl, precision)}"
     if cache and os.path.exists(cache):
         try:
             db = json.load(open(cache))
             if wkey in db:
-                c = db[wkey]["best"]
-                return Candidate(tuple(c["tile"]), c["block"], c["chunk"], c["wg_per_cu"]), db[wkey]["table"]
+                c = dict(db[wkey]["best"])
+                c["tile"] = tuple(c["tile"])
+                return Candidate(**c), db[wkey]["table"]
         except (OSError, ValueError, KeyError):
             pass
     tol = 1e-12 if precision == pic.PIC_FP64 else 1e-5
@@ -110,7 +133,7 @@ def tune(wl, precision=pic.PIC_FP32_SPLIT, space: Optional[List[Candidate]] = No
             table.append((cand.key(), "skipped: budget"))
             continue
         try:
-            ms, E, J = _run(wl, precision, cand, steps, sort_every, stream)
+            ms, E, J = _run(wl, precision, cand, steps, stream)
         except pic.PicError as e:
             table.append((cand.key(), f"rejected: {e}"))
             continue

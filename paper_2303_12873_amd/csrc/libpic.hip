@@ -129,6 +129,11 @@ struct pic_ctx {
     int dims = 0;                   // 3 or 2 if every box has it, else 0
     // graphs
     std::map<std::string, hipGraphExec_t> graphs;
+    // optional timing of the tiled particle kernel (also inside graphs):
+    // device wall-clock stamps written just before and after it
+    bool timing = false, timed = false;
+    long long *stamps = nullptr;    // 2 device values
+    int clock_khz = 0;
     bool capturing = false;
     hipStream_t cap_stream = nullptr;   // private stream graphs are recorded on
 };
@@ -404,12 +409,17 @@ pic_status run_particles(pic_ctx *c, pic_fields *f, pic_species *sp, int nsp, in
         }
     } else {
         HIP_TRY(launch_zero_ints(c->strag_count, nsp, c->stream));
+        if (form == PIC_KERNEL_BATCHED) HIP_TRY(launch_set_int(c->queue, 0, c->stream));
+        if (c->timing) HIP_TRY(launch_stamp(c->stamps, c->stream));
         if (form == PIC_KERNEL_TILED) {
             if (c->nslots > 0) HIP_TRY(launch_particles(c, k, 1, mode, c->nslots, 0));
         } else {
-            HIP_TRY(launch_set_int(c->queue, 0, c->stream));
             int grid = c->cus * c->tun.wg_per_cu;
             HIP_TRY(launch_particles(c, k, 2, mode, grid, 0));
+        }
+        if (c->timing) {
+            HIP_TRY(launch_stamp(c->stamps + 1, c->stream));
+            c->timed = true;
         }
         // particles that had left their tile plus margin since the sort
         HIP_TRY(launch_particles(c, k, 3, mode, c->cus * 2, 0));
@@ -809,6 +819,7 @@ pic_status pic_step(pic_ctx *c, pic_fields *f, pic_species *sp, int32_t nsp, int
     std::string key((const char *)f, sizeof(pic_fields));
     key.append((const char *)c->hsp.data(), c->hsp.size() * sizeof(DevSpecies));
     key.push_back(sort ? 'S' : 'N');
+    key.push_back(c->timing ? 'T' : 'U');
     auto it = c->graphs.find(key);
     if (it == c->graphs.end()) {
         // size every scratch buffer before capture starts
@@ -820,24 +831,26 @@ pic_status pic_step(pic_ctx *c, pic_fields *f, pic_species *sp, int32_t nsp, int
         if (sort && (st = ensure_sort_scratch(c, maxnp, nitems_cap)) != PIC_OK) return st;
         HIP_TRY(hipStreamSynchronize(c->stream));
         if (!c->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+        hipGraphExec_t ex = nullptr;
         hipGraph_t g = nullptr;
         hipStream_t user = c->stream;
         HIP_TRY(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
         c->stream = c->cap_stream;
         c->capturing = true;
+        const bool prev_timed = c->timed;
         pic_status s1 = PIC_OK;
         if (sort) s1 = do_sort(c, sp, nsp, nullptr, nullptr, nullptr);
         if (s1 == PIC_OK) s1 = run_particles(c, f, sp, nsp, MODE_FUSED);
         if (s1 == PIC_OK) s1 = do_fdtd(c, f);
         c->capturing = false;
         c->stream = user;
+        c->timed = prev_timed;       // nothing has run yet
         hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
         if (s1 != PIC_OK) {
             if (g) (void)hipGraphDestroy(g);
             return s1;
         }
         if (e != hipSuccess) return fail(PIC_ERR_DEVICE, std::string("capture: ") + hipGetErrorString(e));
-        hipGraphExec_t ex = nullptr;
         e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
         (void)hipGraphDestroy(g);
         if (e != hipSuccess) return fail(PIC_ERR_DEVICE, std::string("instantiate: ") + hipGetErrorString(e));
@@ -850,6 +863,7 @@ pic_status pic_step(pic_ctx *c, pic_fields *f, pic_species *sp, int32_t nsp, int
         }
     }
     HIP_TRY(hipGraphLaunch(it->second, c->stream));
+    if (c->timing) c->timed = true;
     return PIC_OK;
 }
 
@@ -895,6 +909,7 @@ pic_status pic_free(pic_ctx *c) {
     if (!c) return PIC_OK;
     (void)hipStreamSynchronize(c->stream);
     for (auto &kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+    dfree(c->stamps);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     for (auto &sl : c->slots) {
         for (int d = 0; d < 3; ++d) { dfree(sl.xo[d]); dfree(sl.offo[d]); }
@@ -927,5 +942,30 @@ pic_status pic_free(pic_ctx *c) {
 }
 
 int32_t pic_device_cus(pic_ctx *c) { return c ? c->cus : 0; }
+
+pic_status pic_set_timing(pic_ctx *c, int32_t on) {
+    if (!c) return fail(PIC_ERR_ARG, "ctx is NULL");
+    if (on && !c->stamps) {
+        int dev = 0;
+        HIP_TRY(hipGetDevice(&dev));
+        HIP_TRY(hipDeviceGetAttribute(&c->clock_khz, hipDeviceAttributeWallClockRate, dev));
+        if (c->clock_khz <= 0) return fail(PIC_ERR_DEVICE, "no device wall clock rate");
+        pic_status st = dalloc(&c->stamps, 2);
+        if (st != PIC_OK) return st;
+    }
+    c->timing = on != 0;
+    c->timed = false;
+    return PIC_OK;
+}
+
+pic_status pic_kernel_ms(pic_ctx *c, float *ms) {
+    if (!c || !ms) return fail(PIC_ERR_ARG, "ctx or ms is NULL");
+    if (!c->timed) return fail(PIC_ERR_STATE, "no timed particle kernel since pic_set_timing");
+    long long t[2] = {0, 0};
+    HIP_TRY(hipMemcpyAsync(t, c->stamps, sizeof(t), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    *ms = (float)((double)(t[1] - t[0]) / (double)c->clock_khz);
+    return PIC_OK;
+}
 
 }  // extern "C"

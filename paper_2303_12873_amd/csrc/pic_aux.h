@@ -37,6 +37,7 @@ hipError_t launch_items(const DevSpecies *spt, const int *bprefix, int nb, const
                         const int *box_sp, int nslots, int chunk, int *counts, int *starts,
                         int *scan_scratch, Item *items, int *nitems, int *queue, hipStream_t st);
 hipError_t launch_set_int(int *p, int v, hipStream_t st);
+hipError_t launch_stamp(long long *out, hipStream_t st);
 hipError_t launch_zero_ints(int *p, int n, hipStream_t st);
 hipError_t launch_zero_j(const DevFields &f, const DevBox *boxes, const long long *fp, int nb,
                          long long total, hipStream_t st);

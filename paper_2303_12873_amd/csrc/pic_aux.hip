@@ -333,6 +333,9 @@ __global__ void k_item_fill(const DevSpecies *spt, const int *bprefix, int nb,
 
 __global__ void k_set_int(int *p, int v) { *p = v; }
 
+// The device's constant-rate wall clock, by one thread (a timing stamp).
+__global__ void k_stamp(long long *out) { out[threadIdx.x] = wall_clock64(); }
+
 __global__ void k_zero_ints(int *p, int n) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0;
@@ -587,6 +590,11 @@ hipError_t launch_items(const DevSpecies *spt, const int *bprefix, int nb, const
     hipLaunchKernelGGL(k_item_fill, dim3(blocks_for(nslots, 256)), dim3(256), 0, st, spt, bprefix,
                        nb, box_sp_off, box_sp, nslots, chunk, (const int *)starts, items);
     hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, st, queue, 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_stamp(long long *out, hipStream_t st) {
+    hipLaunchKernelGGL(k_stamp, dim3(1), dim3(1), 0, st, out);
     return hipGetLastError();
 }
 

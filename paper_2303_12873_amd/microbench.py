@@ -54,6 +54,14 @@ def run(cus: int = 256):
     return out
 
 
+def copy_only(nbytes: int = 4 << 30, cus: int = 256):
+    """One timed device copy of nbytes (the calibration run for HBM counters)."""
+    ms = _lib().pic_mb_copy(nbytes, cus * 16)
+    return {"test": "hbm_copy", "bytes": nbytes, "ms": ms, "GB_per_s": 2 * nbytes / (ms * 1e-3) / 1e9}
+
+
 if __name__ == "__main__":
-    for r in run():
+    import sys
+    rows = [copy_only()] if sys.argv[1:] == ["copy"] else run()
+    for r in rows:
         print(json.dumps(r), flush=True)

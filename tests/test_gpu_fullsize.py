@@ -26,7 +26,7 @@ def _gpu():
     ensure_built()
 
 
-def _sampled_parity(wl, precision, kernel, tile, nsample, tol_x, tol_u, tol_cont):
+def _sampled_parity(wl, precision, kernel, tile, nsample, tol_x, tol_u, tol_cont, block, stride):
     box0 = wl.boxes[0]
     box = pi.Box(box0.dim, box0.n, box0.dt, box0.order, tile, box0.dx)
     g = oracle.make_grid(box.dim, box.n, box.dx, box.dt, box.order)
@@ -39,7 +39,9 @@ def _sampled_parity(wl, precision, kernel, tile, nsample, tol_x, tol_u, tol_cont
     E0 = np.ascontiguousarray(wl.E[0].cpu().numpy())
     B0 = np.ascontiguousarray(wl.B[0].cpu().numpy())
 
-    ctx = pic.pic_init([box], precision, kernel=kernel, block=256, chunk=4096, wg_per_cu=2)
+    # the launch configuration bench.py times (defaults of both forms)
+    ctx = pic.pic_init([box], precision, kernel=kernel, block=block, chunk=4096, wg_per_cu=2,
+                       lane_stride=stride)
     f = pic.make_fields([box], wl.E, wl.B, precision)
     sp = [pic.make_species(p, precision) for p in wl.species]
     perms = [torch.empty(s.np, dtype=torch.int32, device="cuda") for s in sp]
@@ -90,10 +92,16 @@ def _sampled_parity(wl, precision, kernel, tile, nsample, tol_x, tol_u, tol_cont
 def test_c5_full_size_split_batched_sampled():
     wl = pi.c5("cuda")
     _sampled_parity(wl, pic.PIC_FP32_SPLIT, pic.PIC_KERNEL_BATCHED, (8, 8, 8), 3000,
-                    tol_x=1e-5, tol_u=1e-5, tol_cont=1e-5)
+                    tol_x=1e-5, tol_u=1e-5, tol_cont=1e-5, block=1024, stride=1)
+
+
+def test_c5_full_size_fp64_plain_sampled():
+    wl = pi.c5("cuda")
+    _sampled_parity(wl, pic.PIC_FP64, pic.PIC_KERNEL_TILED, (8, 8, 4), 3000,
+                    tol_x=1e-12, tol_u=1e-12, tol_cont=1e-12, block=512, stride=4)
 
 
 def test_c2_full_size_fp64_tiled_sampled():
     wl = pi.c2("cuda")
-    _sampled_parity(wl, pic.PIC_FP64, pic.PIC_KERNEL_TILED, (8, 8, 8), 3000,
-                    tol_x=1e-12, tol_u=1e-12, tol_cont=1e-12)
+    _sampled_parity(wl, pic.PIC_FP64, pic.PIC_KERNEL_TILED, (8, 8, 4), 3000,
+                    tol_x=1e-12, tol_u=1e-12, tol_cont=1e-12, block=512, stride=4)

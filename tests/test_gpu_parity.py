@@ -400,3 +400,45 @@ def test_two_species_merged_items(prec, tol, chunk, cell_order, spread):
     E, B, J = run.fields_np()
     assert rel_l2(J, Jo) <= tol and rel_l2(E, Eo) <= tol, (rel_l2(J, Jo), rel_l2(E, Eo))
     run.free()
+
+
+@pytest.mark.parametrize("kernel", ("tiled", "batched"))
+def test_particle_kernel_timing(kernel):
+    """pic_set_timing brackets the tiled particle kernel with device clock
+    stamps, also inside the step graphs; the reported duration is positive
+    and no longer than the whole step measured around it with HIP events."""
+    wl = _small(3, 2, 1801, n=(16, 16, 16), ppc=4)
+    run = GpuRun(wl, pic.PIC_FP32_SPLIT, kernel=KERNELS[kernel])
+    with pytest.raises(pic.PicError):
+        pic.pic_set_timing(run.ctx, True)
+        pic.pic_kernel_ms(run.ctx)
+    run.sort()
+    pic.pic_advance(run.ctx, run.f, run.sp)
+    assert pic.pic_kernel_ms(run.ctx) > 0.0
+    for k in range(5):
+        # graphs with and without a sort, each replayed after the other's capture
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        pic.pic_step(run.ctx, run.f, run.sp, sort=(k % 2 == 0))
+        e1.record()
+        torch.cuda.synchronize()
+        ms = pic.pic_kernel_ms(run.ctx)
+        assert 0.0 < ms <= e0.elapsed_time(e1) * 1.05 + 0.05
+    pic.pic_set_timing(run.ctx, False)
+    run.step()
+    run.check()
+    run.free()
+
+
+def test_autotuner_picks_a_parity_clean_candidate():
+    """The tuner times every candidate of a small space on the same inputs,
+    rejects none that agrees with the first, and returns the fastest."""
+    from paper_2303_12873_amd.autotune import Candidate, tune
+    wl = _small(3, 2, 1901, n=(16, 16, 16), ppc=4, species=("e", "i"))
+    space = [Candidate((8, 8, 8), 256, 4096, 2, 1, 2, 2), Candidate((8, 8, 8), 512, 4096, 2, 1, 1, 3),
+             Candidate((4, 4, 4), 256, 64, 1, 4, -1, 2)]
+    best, table = tune(wl, pic.PIC_FP32_SPLIT, space=space, cache=None, log=lambda *a: None)
+    times = [v for _, v in table]
+    assert all(isinstance(v, float) for v in times), table
+    assert best.key() == min(table, key=lambda kv: kv[1])[0]
