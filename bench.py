@@ -51,8 +51,9 @@ def kernel_source_sha():
     return h.hexdigest()
 
 
-def launch_config(tile, block, stride, cell_order):
-    return f"tile={tuple(tile)} block={block} lane_stride={stride} cell_order={cell_order}"
+def launch_config(tile, block, stride, cell_order, pad):
+    return (f"tile={tuple(tile)} block={block} lane_stride={stride} cell_order={cell_order} "
+            f"pad={pad}")
 
 
 def measured_traffic(workload, config):
@@ -96,7 +97,7 @@ def build_workload(name, device):
 
 
 def run_form(wl, precision, kernel, steps, warmup, sort_every, tile, block, chunk, wg, stride,
-             cell_order=0):
+             cell_order=0, pad=0):
     import torch
     import paper_2303_12873_amd as pic
     import pic_inputs as pi
@@ -107,7 +108,7 @@ def run_form(wl, precision, kernel, steps, warmup, sort_every, tile, block, chun
     with torch.cuda.stream(stream):
         ctx = pic.pic_init(boxes, precision, stream=stream.cuda_stream, kernel=kernel,
                            block=block, chunk=chunk, wg_per_cu=wg, lane_stride=stride,
-                           cell_order=cell_order)
+                           cell_order=cell_order, pad=pad)
         f = pic.make_fields(boxes, wl.E, wl.B, precision)
         sp = [pic.make_species(p, precision) for p in wl.species]
     torch.cuda.synchronize()
@@ -216,6 +217,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cell-order", type=int, default=0,
                     help="FP32 within-tile order without the tuner (-1, 1, 2; 0 = library default)")
+    ap.add_argument("--pad", type=int, default=0,
+                    help="FP32 LDS row padding without the tuner (-1, 0, 1, 2)")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the autotuner (use --tile32/--block/--stride and the default order)")
     ap.add_argument("--tune-budget", type=float, default=120.0, help="autotuner time budget (s)")
@@ -255,13 +258,14 @@ def main():
             args.tile32, args.block, args.chunk = tuple(best.tile), best.block, best.chunk
             args.wg_per_cu, args.stride, cell_order = best.wg_per_cu, best.lane_stride, best.cell_order
             args.sort_every = best.sort_every
+            args.pad = best.pad
             tuned = {"picked": best.key(), "candidates": len(table),
                      "seconds": round(time.time() - t1, 1)}
         log(f"  autotuner: {tuned}")
     log("FP32 split + batched form")
     r32 = run_form(wl, pic.PIC_FP32_SPLIT, pic.PIC_KERNEL_BATCHED, args.steps, args.warmup,
                    args.sort_every, args.tile32, args.block, args.chunk, args.wg_per_cu, args.stride,
-                   cell_order)
+                   cell_order, args.pad)
     log(f"  {r32}")
     r64 = None
     if not args.no_fp64:
@@ -281,7 +285,7 @@ def main():
     tfl = flops_launch / t_adv / 1e12
     f_hbm, f_alu = gbs / PEAK_HBM_GBS, tfl / PEAK_VALU_TFLOPS
     traffic = measured_traffic(wl.name, launch_config(args.tile32, args.block, args.stride,
-                                                       cell_order))
+                                                       cell_order, args.pad))
     if f_alu >= f_hbm:
         roof = {"bound": "alu", "achieved": round(tfl, 3), "peak": PEAK_VALU_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(f_alu, 4), "traffic": traffic,
@@ -303,7 +307,7 @@ def main():
                    "form": "fp32_split_batched_graph", "sort_every": args.sort_every,
                    "tile": list(args.tile32), "block": args.block, "chunk": args.chunk,
                    "wg_per_cu": args.wg_per_cu, "lane_stride": args.stride,
-                   "cell_order": cell_order, "autotuned": tuned},
+                   "cell_order": cell_order, "pad": args.pad, "autotuned": tuned},
         "roofline": roof,
         "breakdown_ms": {"advance": r32["ms_advance"], "sort": r32["ms_sort"],
                          "fdtd": r32["ms_fdtd"]},

@@ -100,9 +100,12 @@ typedef struct {
                             particle (l mod G)*stride + l/G, G = ceil(n/stride),
                             so lanes of one wave fall in distinct cells when
                             stride ~ particles per cell (1..64; 0 = 1) */
-    int32_t pad;         /* 0: pad the row of the LDS current tile so a
-                            wave's lanes hit distinct LDS banks (when it
-                            fits); -1: no padding */
+    int32_t pad;         /* Row padding of the LDS tiles, so that a wave's
+                            lanes (a block of tile rows) hit distinct LDS
+                            banks.  0: current tile rows, when it fits;
+                            1: field tile rows, then current tile rows, each
+                            when it fits; 2: both, staging no margin if that
+                            is what makes both fit; -1: no padding */
     int32_t cell_order;  /* Order of the particles inside a tile after
                             pic_sort_tiles.  -1: previous order (tile id
                             only).  1: by class (lx+ly+lz) mod 4 of the

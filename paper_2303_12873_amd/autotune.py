@@ -35,10 +35,11 @@ class Candidate:
     lane_stride: int = 1
     cell_order: int = 2
     sort_every: int = 8
+    pad: int = 0
 
     def key(self):
         return (f"t{self.tile}-b{self.block}-c{self.chunk}-w{self.wg_per_cu}-s{self.lane_stride}"
-                f"-o{self.cell_order}-e{self.sort_every}")
+                f"-o{self.cell_order}-e{self.sort_every}-p{self.pad}")
 
 
 def default_space(dim3: bool, precision=pic.PIC_FP32_SPLIT, sort_every=(8, 16)):
@@ -52,7 +53,8 @@ def default_space(dim3: bool, precision=pic.PIC_FP32_SPLIT, sort_every=(8, 16)):
     for t, b, e in itertools.product(tiles, blocks, sort_every):
         out.append(Candidate(t, b, 4096, 2, 1, 2, e))
         out.append(Candidate(t, b, 4096, 2, 1, 1, e))
-        out.append(Candidate(t, b, 4096, 2, 4, -1, e))
+        for pad in (0, 1):
+            out.append(Candidate(t, b, 4096, 2, 4, -1, e, pad))
     return out
 
 
@@ -76,7 +78,7 @@ def _run(wl, precision, cand: Candidate, steps: int, stream, warm: int = 4):
         ctx = pic.pic_init(boxes, precision, stream=stream.cuda_stream,
                            kernel=pic.PIC_KERNEL_BATCHED, block=cand.block, chunk=cand.chunk,
                            wg_per_cu=cand.wg_per_cu, lane_stride=cand.lane_stride,
-                           cell_order=cand.cell_order)
+                           cell_order=cand.cell_order, pad=cand.pad)
         f = pic.make_fields(boxes, wl.E, wl.B, precision)
         sp = [pic.make_species(p, precision) for p in wl.species]
     try:

@@ -96,6 +96,7 @@ struct pic_ctx {
     size_t lds_field_bytes = 0, lds_bytes = 0;
     int margin = 0;                 // cells staged around each tile
     int jrow = 0;                   // padded row length of the LDS current tile (0 = none)
+    int frow = 0;                   // padded row length of the LDS field tile (0 = none)
     // species
     std::vector<Slot> slots;
     std::vector<DevSpecies> hsp;    // last uploaded table
@@ -356,6 +357,7 @@ KParams make_params(pic_ctx *c, const pic_fields *f, int nsp) {
     k.lane_stride = c->tun.lane_stride;
     k.margin = c->margin;
     k.jrow = c->jrow;
+    k.frow = c->frow;
     k.strag_count = c->strag_count;
     k.box_sp_off = c->dbox_sp_off;
     k.box_sp = c->dbox_sp;
@@ -656,7 +658,6 @@ pic_status pic_init(pic_ctx **out, const pic_box_desc *boxes, int32_t nboxes, pi
     }
     const int o = c->order;
     const size_t fb = prec == PIC_FP64 ? 8 : 4;
-    size_t fmax = 0, jmax = 0, fmax1 = 0, jmax1 = 0;   // without / with a 1-cell margin
     c->hfp.assign(nboxes + 1, 0);
     for (int i = 0; i < nboxes; ++i) {
         const pic_box_desc &b = boxes[i];
@@ -666,8 +667,6 @@ pic_status pic_init(pic_ctx **out, const pic_box_desc *boxes, int32_t nboxes, pi
         d.order = b.order;
         d.ncells = 1;
         d.small = 0;
-        size_t fr = 6 * fb, jr = 3 * 8;   // the LDS current tile is FP64 in both forms
-        size_t fr1 = fr, jr1 = jr;
         for (int k = 0; k < 3; ++k) {
             d.n[k] = b.n[k];
             d.tile[k] = b.tile[k];
@@ -675,24 +674,13 @@ pic_status pic_init(pic_ctx **out, const pic_box_desc *boxes, int32_t nboxes, pi
             d.dx[k] = b.dx[k];
             d.ncells *= b.n[k];
             const bool active = !(b.dim == 2 && k == 1);
-            if (active) {
-                int te = std::min(b.tile[k], b.n[k]);
-                fr *= (size_t)(te + halo_gl(o) + halo_gh(o));
-                jr *= (size_t)(te + halo_jl(o) + halo_jh(o));
-                fr1 *= (size_t)(te + halo_gl(o) + halo_gh(o) + 2);
-                jr1 *= (size_t)(te + halo_jl(o) + halo_jh(o) + 2);
-                if (b.n[k] < 8) d.small = 1;
-            }
+            if (active && b.n[k] < 8) d.small = 1;
         }
         d.ntiles = d.nt[0] * d.nt[1] * d.nt[2];
         d.cell_base = b.cell_base;
         d.dt = b.dt;
         d.inv_nx = 1.0 / (double)b.n[0];
         d.inv_nxy = 1.0 / ((double)b.n[0] * (double)b.n[1]);
-        fmax = std::max(fmax, fr);
-        jmax = std::max(jmax, jr);
-        fmax1 = std::max(fmax1, fr1);
-        jmax1 = std::max(jmax1, jr1);
         c->hbox.push_back(d);
         c->hfp[i + 1] = c->hfp[i] + d.ncells;
     }
@@ -702,40 +690,67 @@ pic_status pic_init(pic_ctx **out, const pic_box_desc *boxes, int32_t nboxes, pi
         for (int i = 0; i < nboxes; ++i) n3 += boxes[i].dim == 3;
         c->dims = n3 == nboxes ? 3 : (n3 == 0 ? 2 : 0);
     }
-    // Stage a 1-cell margin around every tile when it fits in LDS.
-    if ((fmax1 + 15) / 16 * 16 + jmax1 <= (size_t)LDS_BYTES_MAX) {
-        c->margin = 1;
-        fmax = fmax1;
-        jmax = jmax1;
-    }
-    c->lds_field_bytes = (fmax + 15) / 16 * 16;
-    c->lds_bytes = c->lds_field_bytes + jmax;
-    // Pad the row of the LDS current tile to the smallest length >= the
-    // tile row that is an odd multiple of the tile width modulo 32 FP64
-    // slots: a wave's lanes spread over a block of tile rows then land on
-    // distinct LDS banks (the FP64 atomic rate halves per 2-way conflict).
-    if (t.pad >= 0) {
-        int tx = 0, need = 0;
-        size_t jpad = 0;
-        for (int i = 0; i < nboxes; ++i) tx = std::max(tx, std::min(boxes[i].tile[0], boxes[i].n[0]));
-        if (tx > 0 && 32 % tx == 0 && tx < 32) {
-            need = tx + halo_jl(o) + halo_jh(o) + 2 * c->margin;
-            int row = need;
-            while (!((row % 32) % tx == 0 && ((row % 32) / tx) % 2 == 1)) ++row;
-            for (int i = 0; i < nboxes; ++i) {
-                const pic_box_desc &b = boxes[i];
-                size_t jr = 3 * 8 * (size_t)row;
-                for (int k = 1; k < 3; ++k) {
-                    if (b.dim == 2 && k == 1) continue;
-                    jr *= (size_t)(std::min(b.tile[k], b.n[k]) + halo_jl(o) + halo_jh(o) + 2 * c->margin);
-                }
-                jpad = std::max(jpad, jr);
+    // LDS layout: a 1-cell margin around every tile when it fits, and rows
+    // padded (t.pad) so that a wave's lanes, which sit on a block of tile
+    // rows, hit distinct LDS banks.
+    int tx = 0;
+    for (int i = 0; i < nboxes; ++i) tx = std::max(tx, std::min(boxes[i].tile[0], boxes[i].n[0]));
+    // Smallest row >= need that is an odd multiple of tx modulo the row
+    // elements one pass over the 64 banks holds (64 FP32, 32 FP64); 0 if
+    // none within 2x need.
+    auto pad_row = [&](int need, int per_pass) {
+        if (tx <= 0 || tx >= per_pass || per_pass % tx) return 0;
+        int row = need;
+        while (!((row % per_pass) % tx == 0 && ((row % per_pass) / tx) % 2 == 1)) ++row;
+        return row <= 2 * need ? row : 0;
+    };
+    // LDS bytes of the field (F) or current (J) stage for a margin and a
+    // padded row length (0 = unpadded), max over the boxes.
+    auto stage_bytes = [&](bool field, int mg, int row) {
+        size_t mx = 0;
+        for (int i = 0; i < nboxes; ++i) {
+            const pic_box_desc &b = boxes[i];
+            const int lo = field ? halo_gl(o) : halo_jl(o), hi = field ? halo_gh(o) : halo_jh(o);
+            size_t by = field ? 6 * fb : 3 * 8;   // the current tile is FP64 in both forms
+            for (int k = 0; k < 3; ++k) {
+                if (b.dim == 2 && k == 1) continue;
+                size_t w = (size_t)(std::min(b.tile[k], b.n[k]) + lo + hi + 2 * mg);
+                if (k == 0 && row > 0) w = std::max(w, (size_t)row);
+                by *= w;
             }
-            if (row <= 2 * need && c->lds_field_bytes + jpad <= (size_t)LDS_BYTES_MAX) {
-                c->jrow = row;
-                c->lds_bytes = c->lds_field_bytes + jpad;
+            mx = std::max(mx, by);
+        }
+        return field ? (mx + 15) / 16 * 16 : mx;
+    };
+    const int fpass = fb == 4 ? 64 : 32;
+    auto layout = [&](int mg, bool padf, bool padj, int &frow, int &jrow) {
+        frow = padf ? pad_row(tx + halo_gl(o) + halo_gh(o) + 2 * mg, fpass) : 0;
+        jrow = padj ? pad_row(tx + halo_jl(o) + halo_jh(o) + 2 * mg, 32) : 0;
+        return stage_bytes(true, mg, frow) + stage_bytes(false, mg, jrow);
+    };
+    {
+        const size_t cap = (size_t)LDS_BYTES_MAX;
+        int fr = 0, jr = 0;
+        c->margin = layout(1, false, false, fr, jr) <= cap ? 1 : 0;
+        bool padf = false, padj = false;
+        if (t.pad >= 0) {
+            // pad 0: current rows; 1: field rows, then current rows, each
+            // where it fits; 2: both, dropping the margin if need be
+            padj = layout(c->margin, false, true, fr, jr) <= cap && jr > 0;
+            if (t.pad >= 1) {
+                if (layout(c->margin, true, padj, fr, jr) <= cap && fr > 0) padf = true;
+                else if (layout(c->margin, true, false, fr, jr) <= cap && fr > 0) { padf = true; padj = false; }
+                if (t.pad == 2 && !(padf && padj) && c->margin == 1 &&
+                    layout(0, true, true, fr, jr) <= cap && fr > 0 && jr > 0) {
+                    c->margin = 0;
+                    padf = padj = true;
+                }
             }
         }
+        c->lds_bytes = layout(c->margin, padf, padj, fr, jr);
+        c->frow = fr;
+        c->jrow = jr;
+        c->lds_field_bytes = stage_bytes(true, c->margin, fr);
     }
     if (t.kernel != PIC_KERNEL_DIRECT && c->lds_bytes > (size_t)LDS_BYTES_MAX) {
         delete c;

@@ -80,6 +80,7 @@ struct KParams {
     int lane_stride;          // lane -> particle stride inside a work item
     int margin;               // cells staged around each tile (0 or 1)
     int jrow;                 // minimum row length of the LDS current tile
+    int frow;                 // minimum row length of the LDS field tile
     int *strag_count;         // per species: entries in its straggler list
     // species of each box (CSR: box_sp[box_sp_off[b] .. box_sp_off[b+1]))
     const int *box_sp_off;

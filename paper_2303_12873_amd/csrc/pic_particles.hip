@@ -716,14 +716,19 @@ __device__ __forceinline__ void deposit_converged(const JA &ja, const int c0[3],
     const int exu = wave_any(lastx) ? K - 1 : K - 2;
     const int ezu = wave_any(lastz) ? K - 1 : K - 2;
     const int eyu = wave_any(lasty) ? K - 1 : K - 2;
-    R px[K - 1], py[K - 1], pz[K - 1];
+    // Prefix sums of a line's edge values, scaled by the particle's charge
+    // factor.  Without quad pooling they are kept in the LDS accumulation
+    // type, so a line's products need one conversion (of t), not one per
+    // edge; pooled quads combine them in R first.
+    using PV = typename std::conditional<QUAD, R, A>::type;
+    PV px[K - 1], py[K - 1], pz[K - 1];
     {
         R a = R(0), b = R(0), c = R(0);
 #pragma unroll
         for (int i = 0; i < K - 1; ++i) {
-            a += wx.dS[i]; px[i] = (i < K - 2 || lastx) ? cq[0] * a : R(0);
-            c += wz.dS[i]; pz[i] = (i < K - 2 || lastz) ? cq[2] * c : R(0);
-            if (DIM == 3) { b += wy.dS[i]; py[i] = (i < K - 2 || lasty) ? cq[1] * b : R(0); }
+            a += wx.dS[i]; px[i] = (i < K - 2 || lastx) ? (PV)(cq[0] * a) : PV(0);
+            c += wz.dS[i]; pz[i] = (i < K - 2 || lastz) ? (PV)(cq[2] * c) : PV(0);
+            if (DIM == 3) { b += wy.dS[i]; py[i] = (i < K - 2 || lasty) ? (PV)(cq[1] * b) : PV(0); }
         }
     }
     bool pool = false;
@@ -739,10 +744,11 @@ __device__ __forceinline__ void deposit_converged(const JA &ja, const int c0[3],
     const bool lead = (threadIdx.x & 3) == 0;
     // One line of up to 4 edges, `ne` of them written (wave-uniform), at
     // addresses base + e * stride.  Pooled quads: lane r adds edge r.
-    auto line_put = [&](A *base, int stride, const R *pv, R t, int ne) {
-        R v[4];
+    auto line_put = [&](A *base, int stride, const PV *pv, R t, int ne) {
+        PV v[4];
+        const PV tv = (PV)t;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) v[e] = (e < K - 1 && e < ne) ? pv[e] * t : R(0);
+        for (int e = 0; e < 4; ++e) v[e] = (e < K - 1 && e < ne) ? pv[e] * tv : PV(0);
         if constexpr (QUAD) {
             const R sc = quad_reduce_scatter(v);
             const int r = threadIdx.x & 3;
@@ -764,7 +770,7 @@ __device__ __forceinline__ void deposit_converged(const JA &ja, const int c0[3],
         } else {
 #pragma unroll
             for (int e = 0; e < K - 1; ++e)
-                if (e < ne && v[e] != R(0)) unsafeAtomicAdd(base + e * stride, (A)v[e]);
+                if (e < ne && v[e] != PV(0)) unsafeAtomicAdd(base + e * stride, (A)v[e]);
         }
     };
     auto put = [&](A *addr, R v) {
@@ -1105,7 +1111,10 @@ __device__ __forceinline__ void process_item(const KParams &prm, const Item &it,
     lf.base = (const FT *)smem;
     tile.mg = prm.margin;
     const int GL = H::GL + tile.mg, GW = H::GL + H::GH + 2 * tile.mg;
-    lf.o0 = tile.t0[0] - GL; lf.L0 = tile.te[0] + GW;
+    // Row length of the LDS field tile: padded (prm.frow) like the current
+    // tile's; only the first W entries of a row are staged.
+    const int W = tile.te[0] + GW;
+    lf.o0 = tile.t0[0] - GL; lf.L0 = max(W, prm.frow);
     lf.o2 = tile.t0[2] - GL;
     int L2 = tile.te[2] + GW;
     if (DIM == 3) { lf.o1 = tile.t0[1] - GL; lf.L1 = tile.te[1] + GW; }
@@ -1129,6 +1138,7 @@ __device__ __forceinline__ void process_item(const KParams &prm, const Item &it,
         const int n = 6 * lf.L012;
         RegionWalk w(tid, bs, lf.L0, lf.L1, L2);
         for (int idx = tid; idx < n; idx += bs, w.next()) {
+            if (w.i >= W) continue;
             int gi = lf.o0 + w.i, gj = lf.o1 + w.j, gk = lf.o2 + w.k;
             if (any) { gi = wrap_index_any(gi, b.n[0]); gj = wrap_index_any(gj, b.n[1]); gk = wrap_index_any(gk, b.n[2]); }
             else { gi = wrap_index(gi, b.n[0]); gj = wrap_index(gj, b.n[1]); gk = wrap_index(gk, b.n[2]); }

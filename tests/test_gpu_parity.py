@@ -442,3 +442,23 @@ def test_autotuner_picks_a_parity_clean_candidate():
     times = [v for _, v in table]
     assert all(isinstance(v, float) for v in times), table
     assert best.key() == min(table, key=lambda kv: kv[1])[0]
+
+
+@pytest.mark.parametrize("prec,tol", ((pic.PIC_FP64, TOL64), (pic.PIC_FP32_SPLIT, TOL32)))
+@pytest.mark.parametrize("pad", (-1, 0, 1, 2))
+def test_padded_lds_rows(prec, tol, pad):
+    """Every LDS row-padding mode (field rows, current rows, both without
+    the margin) gives the oracle's fields after a few steps with drift."""
+    wl = pi.uniform_box((16, 16, 12), 4, 0.05, 0.3, 3, 2100, "cpu", tile=(8, 8, 4),
+                        fields="fourier", species=("e", "i"))
+    Eo, Bo, Jo, sps = _oracle_steps(wl, 3)
+    run = GpuRun(wl, prec, kernel=pic.PIC_KERNEL_BATCHED, lane_stride=4, cell_order=-1, pad=pad,
+                 block=512)
+    run.sort()
+    for _ in range(3):
+        run.particles()
+        pic.pic_fdtd_step(run.ctx, run.f)
+    run.check()
+    E, B, J = run.fields_np()
+    assert rel_l2(J, Jo) <= tol and rel_l2(E, Eo) <= tol, (rel_l2(J, Jo), rel_l2(E, Eo))
+    run.free()
