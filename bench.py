@@ -225,7 +225,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
-              "slab decomposition is a design, not part of this build.", file=sys.stderr)
+              "slab decomposition is not implemented.", file=sys.stderr)
         sys.exit(2)
 
     import torch
