@@ -118,8 +118,11 @@ typedef struct {
                             groups of four of every cell followed by each
                             cell's last (count mod 4) particles, so that
                             aligned groups of four share a cell (the quad
-                            pooling of the deposit at lane_stride 1).  1 and
-                            2 apply when tile id and cell fit a 31-bit key.
+                            pooling of the deposit at lane_stride 1).  3: by
+                            the cell lx + tx*(ly + ty*lz) alone, ties stable
+                            (restores the cell-major order that lane_stride
+                            4 spreads over distinct cells).  1..3 apply when
+                            tile id and cell fit a 31-bit key.
                             0 = default: 2 for BATCHED, else -1. */
     int32_t quad_spread; /* TILED/BATCHED at lane_stride 1: 1 = the 16 quads
                             of a wave are taken ceil(nquads/16) quads apart

@@ -78,6 +78,7 @@ def lib():
         L.orc_cell_order_keys.argtypes = [C.POINTER(Grid), _P, _I, C.POINTER(Species), _P]
         L.orc_stable_perm.argtypes = [C.c_int64, _P, _P]
         L.orc_quad_order.argtypes = [C.c_int64, _P, _I, _P]
+        L.orc_tile_cell_keys.argtypes = [C.POINTER(Grid), _P, _I, C.POINTER(Species), _P]
         _lib = L
     return _lib
 
@@ -233,6 +234,15 @@ def cell_order_keys(g: Grid, tile, cbits, sp):
     t = np.ascontiguousarray(tile, dtype=np.int32)
     key = np.zeros(st.np, dtype=np.int64)
     lib().orc_cell_order_keys(C.byref(g), t.ctypes.data, int(cbits), C.byref(st), key.ctypes.data)
+    return key
+
+
+def tile_cell_keys(g: Grid, tile, cbits, sp):
+    """Cell order without classes (int64 keys), see orc_tile_cell_keys."""
+    st = _species_struct(sp)
+    t = np.ascontiguousarray(tile, dtype=np.int32)
+    key = np.zeros(st.np, dtype=np.int64)
+    lib().orc_tile_cell_keys(C.byref(g), t.ctypes.data, int(cbits), C.byref(st), key.ctypes.data)
     return key
 
 

@@ -461,6 +461,25 @@ void orc_cell_order_keys(const orc_grid *g, const int32_t tile[3], int32_t cbits
     }
 }
 
+void orc_tile_cell_keys(const orc_grid *g, const int32_t tile[3], int32_t cbits,
+                        const orc_species *S, int64_t *key)
+{
+    int64_t nt[3];
+    for (int d = 0; d < 3; ++d) nt[d] = (g->n[d] + tile[d] - 1) / tile[d];
+    const int64_t t1 = g->dim == 3 ? tile[1] : 1;
+    for (int64_t p = 0; p < S->np; ++p) {
+        int64_t t[3], l[3];
+        for (int d = 0; d < 3; ++d) {
+            if (g->dim == 2 && d == 1) { t[d] = 0; l[d] = 0; continue; }
+            int64_t c = wrapi((int64_t)floor(S->x[d][p]), g->n[d]);
+            t[d] = c / tile[d];
+            l[d] = c - t[d] * tile[d];
+        }
+        const int64_t id = t[0] + nt[0] * (t[1] + nt[1] * t[2]);
+        key[p] = (id << cbits) | (l[0] + tile[0] * (l[1] + t1 * l[2]));
+    }
+}
+
 static const int64_t *g_sort_key64;
 
 static int by_key64_then_index(const void *a, const void *b)

@@ -125,6 +125,11 @@ void orc_stable_sort(int64_t np, const int32_t *key, int32_t nkeys,
 void orc_cell_order_keys(const orc_grid *g, const int32_t tile[3], int32_t cbits,
                          const orc_species *sp, int64_t *key);
 
+/* Cell order without classes: key = tile id << cbits | (lx + tile[0]*(ly +
+ * t1*lz)), the same tile-local cell index as orc_cell_order_keys. */
+void orc_tile_cell_keys(const orc_grid *g, const int32_t tile[3], int32_t cbits,
+                        const orc_species *sp, int64_t *key);
+
 /* Stable sort of particle indices by a 64-bit key (ties in index order). */
 void orc_stable_perm(int64_t np, const int64_t *key, int32_t *perm);
 

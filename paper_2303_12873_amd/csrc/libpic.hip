@@ -511,14 +511,17 @@ pic_status do_sort(pic_ctx *c, const pic_species *sp, int nsp, int32_t *const *p
         const int nkeys = b.ntiles + 1;
         Slot &sl = c->slots[s];
         // cell bits of the within-tile order (0: tile id only)
+        // (cell_order 1/2 add two class bits; 3 orders by cell alone)
         int cb = 0;
+        const int classes = c->tun.cell_order == 3 ? 0 : 1;
         if (c->tun.cell_order) {
             const int vol = b.tile[0] * (b.dim == 3 ? b.tile[1] : 1) * b.tile[2];
             cb = key_bits(vol);
-            if (key_bits(nkeys) + cb + 2 > 31) cb = 0;
+            if (key_bits(nkeys) + cb + 2 * classes > 31) cb = 0;
         }
-        const int shift = cb ? cb + 2 : 0;
-        HIP_TRY(launch_tile_keys(prec, c->dsp, s, np, c->dbox, cb, c->keys[0], c->vals[0], c->derr, S));
+        const int shift = cb ? cb + 2 * classes : 0;
+        HIP_TRY(launch_tile_keys(prec, c->dsp, s, np, c->dbox, cb, classes, c->keys[0], c->vals[0],
+                                 c->derr, S));
         const int passes = (key_bits(nkeys) + shift + 7) / 8;
         int cur = 0;
         for (int ps = 0; ps < passes; ++ps) {
@@ -641,7 +644,7 @@ pic_status pic_init(pic_ctx **out, const pic_box_desc *boxes, int32_t nboxes, pi
     if (t.chunk < 1) return fail(PIC_ERR_ARG, "chunk must be >= 1");
     if (t.wg_per_cu < 1 || t.wg_per_cu > 64) return fail(PIC_ERR_ARG, "wg_per_cu must be 1..64");
     if (t.lane_stride < 1 || t.lane_stride > 64) return fail(PIC_ERR_ARG, "lane_stride must be 1..64");
-    if (t.cell_order < -1 || t.cell_order > 2) return fail(PIC_ERR_ARG, "cell_order must be -1..2");
+    if (t.cell_order < -1 || t.cell_order > 3) return fail(PIC_ERR_ARG, "cell_order must be -1..3");
     t.cell_order = t.cell_order == 0 ? (t.kernel == PIC_KERNEL_BATCHED ? 2 : 0) : std::max(t.cell_order, 0);
 
     pic_ctx *c = new pic_ctx();

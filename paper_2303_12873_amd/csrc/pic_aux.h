@@ -6,10 +6,11 @@
 namespace pic {
 
 // Sort keys: the tile id, or with cbits > 0 (tile id, cell class, cell in
-// tile) packed as tile << (cbits + 2) | class << cbits | cell.
+// tile) packed as tile << (cbits + 2) | class << cbits | cell (classes != 0)
+// or tile << cbits | cell (classes == 0).
 hipError_t launch_tile_keys(int prec, const DevSpecies *spt, int s, long long np,
-                            const DevBox *boxes, int cbits, int *key, int *val, int *err,
-                            hipStream_t st);
+                            const DevBox *boxes, int cbits, int classes, int *key, int *val,
+                            int *err, hipStream_t st);
 size_t scan_scratch_ints(long long n);
 hipError_t scan_exclusive(const int *in, int *out, long long n, int *total, int *scratch,
                           hipStream_t st);

@@ -24,7 +24,7 @@ __device__ inline int wave_id() { return threadIdx.x >> 6; }
 
 template <int PREC>
 __global__ void k_tile_keys(const DevSpecies *spt, int s, const DevBox *boxes, int cbits,
-                            int *key, int *val, int *err) {
+                            int classes, int *key, int *val, int *err) {
     const DevSpecies &sp = spt[s];
     const DevBox &b = boxes[sp.box];
     long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -58,11 +58,12 @@ __global__ void k_tile_keys(const DevSpecies *spt, int s, const DevBox *boxes, i
             const int lx = c[0] - tx * b.tile[0], ly = c[1] - ty * b.tile[1],
                       lz = c[2] - tz * b.tile[2];
             const int within = lx + b.tile[0] * (ly + (b.dim == 3 ? b.tile[1] : 1) * lz);
-            k = (k << (cbits + 2)) | (((lx + ly + lz) & 3) << cbits) | within;
+            if (classes) k = (k << (cbits + 2)) | (((lx + ly + lz) & 3) << cbits) | within;
+            else k = (k << cbits) | within;
         }
     } else {
         // bucket of invalid particles, after every tile
-        k = cbits > 0 ? (b.ntiles << (cbits + 2)) : b.ntiles;
+        k = cbits > 0 ? (b.ntiles << (cbits + (classes ? 2 : 0))) : b.ntiles;
         atomicOr(err, 1);
     }
     key[i] = k;
@@ -451,15 +452,15 @@ inline unsigned blocks_for(long long n, int bs) { return (unsigned)((n + bs - 1)
 // ============================================================ host launchers
 
 hipError_t launch_tile_keys(int prec, const DevSpecies *spt, int s, long long np,
-                            const DevBox *boxes, int cbits, int *key, int *val, int *err,
-                            hipStream_t st) {
+                            const DevBox *boxes, int cbits, int classes, int *key, int *val,
+                            int *err, hipStream_t st) {
     if (np == 0) return hipSuccess;
     if (prec == 0)
         hipLaunchKernelGGL(k_tile_keys<0>, dim3(blocks_for(np, 256)), dim3(256), 0, st, spt, s,
-                           boxes, cbits, key, val, err);
+                           boxes, cbits, classes, key, val, err);
     else
         hipLaunchKernelGGL(k_tile_keys<1>, dim3(blocks_for(np, 256)), dim3(256), 0, st, spt, s,
-                           boxes, cbits, key, val, err);
+                           boxes, cbits, classes, key, val, err);
     return hipGetLastError();
 }
 

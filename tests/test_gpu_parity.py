@@ -154,14 +154,19 @@ def _oracle_sort(box, ref, cell_order):
         vol = box.tile[0] * (box.tile[1] if box.dim == 3 else 1) * box.tile[2]
         cb = _key_bits(vol)
         assert _key_bits(box.ntiles + 1) + cb + 2 <= 31
-        ck = oracle.cell_order_keys(_grid(box), box.tile, cb, ref) if ref.x.shape[1] else np.zeros(0, np.int64)
-        perm_o = oracle.quad_order(ck, cb) if cell_order == 2 else oracle.stable_perm(ck)
+        if not ref.x.shape[1]:
+            perm_o = np.zeros(0, np.int32)
+        elif cell_order == 3:
+            perm_o = oracle.stable_perm(oracle.tile_cell_keys(_grid(box), box.tile, cb, ref))
+        else:
+            ck = oracle.cell_order_keys(_grid(box), box.tile, cb, ref)
+            perm_o = oracle.quad_order(ck, cb) if cell_order == 2 else oracle.stable_perm(ck)
     return perm_o, key, off_o
 
 
 @pytest.mark.parametrize("case", ["random", "one_tile", "sparse", "ragged2d", "empty"])
 @pytest.mark.parametrize("prec", (pic.PIC_FP64, pic.PIC_FP32_SPLIT))
-@pytest.mark.parametrize("cell_order", (-1, 1, 2))
+@pytest.mark.parametrize("cell_order", (-1, 1, 2, 3))
 def test_sort_bit_exact(case, prec, cell_order):
     seeds = {"random": 1, "one_tile": 2, "sparse": 3, "ragged2d": 4, "empty": 5}
     rng = np.random.default_rng(seeds[case])
@@ -202,7 +207,7 @@ def test_sort_bit_exact(case, prec, cell_order):
     run.free()
 
 
-@pytest.mark.parametrize("cell_order", (-1, 1, 2))
+@pytest.mark.parametrize("cell_order", (-1, 1, 2, 3))
 def test_sort_large_multi_pass(cell_order):
     """~2 M particles, 2^15 tiles: two radix passes (tile id) or three (with
     the cell order), many sort blocks."""

@@ -351,3 +351,23 @@ def test_quad_order():
         assert all(v < 4 and v == counts[k] % 4 for k, v in rest.items())
         assert (np.diff(rank_in_base[first]) > 0).all()
         assert (np.diff(rank_in_base[second]) > 0).all()
+
+
+def test_tile_cell_keys():
+    """Cell order without classes: the tile part is the tile id, equal keys
+    mean equal cells, and within a tile the keys enumerate the cells x
+    fastest (checked on every cell of a 2-tile box)."""
+    n = (8, 4, 8)
+    g = oracle.make_grid(3, n, (1.0, 1.0, 1.0), 0.5, 1)
+    cells = np.stack(np.meshgrid(*[np.arange(k) for k in n], indexing="ij")).reshape(3, -1)
+    x = cells + 0.25
+    sp = _sp(x, np.zeros_like(x), np.ones(x.shape[1]))
+    key = oracle.tile_cell_keys(g, (8, 4, 4), 7, sp)
+    assert np.array_equal(key >> 7, oracle.tile_keys(g, (8, 4, 4), sp))
+    assert len(set(key.tolist())) == x.shape[1]
+    order = np.argsort(key, kind="stable")
+    first_tile = order[:128]
+    c = cells[:, first_tile]
+    assert np.array_equal(c[0], np.tile(np.arange(8), 16))
+    assert np.array_equal(c[1], np.tile(np.repeat(np.arange(4), 8), 4))
+    assert np.array_equal(c[2], np.repeat(np.arange(4), 32))
