@@ -645,6 +645,8 @@ pic_status pic_init(pic_ctx **out, const pic_box_desc *boxes, int32_t nboxes, pi
     if (t.wg_per_cu < 1 || t.wg_per_cu > 64) return fail(PIC_ERR_ARG, "wg_per_cu must be 1..64");
     if (t.lane_stride < 1 || t.lane_stride > 64) return fail(PIC_ERR_ARG, "lane_stride must be 1..64");
     if (t.cell_order < -1 || t.cell_order > 3) return fail(PIC_ERR_ARG, "cell_order must be -1..3");
+    if (t.pad < -1 || t.pad > 2) return fail(PIC_ERR_ARG, "pad must be -1..2");
+    if (t.quad_spread < -1 || t.quad_spread > 1) return fail(PIC_ERR_ARG, "quad_spread must be -1..1");
     t.cell_order = t.cell_order == 0 ? (t.kernel == PIC_KERNEL_BATCHED ? 2 : 0) : std::max(t.cell_order, 0);
 
     pic_ctx *c = new pic_ctx();

@@ -59,6 +59,19 @@ def test_pic_init_rejects_bad_boxes_on_the_host(kw, status):
     assert e.value.status == status
 
 
+@pytest.mark.parametrize("kw", [dict(block=96), dict(block=2048), dict(lane_stride=65),
+                                dict(cell_order=4), dict(cell_order=-2), dict(pad=3),
+                                dict(pad=-2), dict(quad_spread=2), dict(wg_per_cu=65),
+                                dict(kernel=3)])
+def test_pic_init_rejects_bad_tuning_on_the_host(kw):
+    ensure_built()
+    args = dict(kernel=pic.PIC_KERNEL_BATCHED)
+    args.update(kw)
+    with pytest.raises(pic.PicError) as e:
+        pic.pic_init([_Box()], pic.PIC_FP32_SPLIT, stream=0, **args)
+    assert e.value.status == pic.PIC_ERR_ARG
+
+
 def test_mixed_orders_rejected():
     ensure_built()
     with pytest.raises(pic.PicError) as e:
