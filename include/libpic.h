@@ -66,10 +66,11 @@ typedef enum {
                                in LDS, J accumulated in an FP64 LDS tile then
                                flushed with FP64 global atomics (needs
                                pic_sort_tiles).  The staged region carries a
-                               1-cell margin when it fits in LDS, so particles
-                               that drifted up to one cell out of their tile
-                               since the sort stay on the LDS path; beyond
-                               that they use global memory. */
+                               1-cell margin on every axis where it fits in
+                               LDS (given up on the widest tile edges first),
+                               so particles that drifted up to one cell out
+                               of their tile since the sort stay on the LDS
+                               path; beyond that they use global memory. */
     PIC_KERNEL_BATCHED = 2  /* as TILED, but a persistent grid walks a work
                                queue so uneven tiles and many boxes share one
                                launch: one item per box tile covers every
@@ -104,8 +105,8 @@ typedef struct {
                             lanes (a block of tile rows) hit distinct LDS
                             banks.  0: current tile rows, when it fits;
                             1: field tile rows, then current tile rows, each
-                            when it fits; 2: both, staging no margin if that
-                            is what makes both fit; -1: no padding */
+                            when it fits; 2: both, giving up margin axes if
+                            that is what makes both fit; -1: no padding */
     int32_t cell_order;  /* Order of the particles inside a tile after
                             pic_sort_tiles.  -1: previous order (tile id
                             only).  1: by class (lx+ly+lz) mod 4 of the

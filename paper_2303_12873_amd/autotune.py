@@ -48,14 +48,16 @@ def default_space(dim3: bool, precision=pic.PIC_FP32_SPLIT, sort_every=(8, 16)):
     strides 1 (quad-pooled deposit) and 4 with the within-tile orders that
     suit them, and sort intervals.  Field-row padding (pad 1, 2) never beat
     the current-row padding on the workloads measured and is left out."""
-    tiles = [(8, 8, 8), (8, 8, 4)] if dim3 else [(8, 1, 8), (16, 1, 16)]
+    tiles = [(8, 8, 4), (16, 8, 4), (8, 8, 8)] if dim3 else [(8, 1, 8), (16, 1, 16)]
     blocks = [1024] if precision == pic.PIC_FP32_SPLIT else [512]
     out = []
-    for t, b, e in itertools.product(tiles, blocks, sort_every):
-        out.append(Candidate(t, b, 4096, 2, 1, 2, e))
-        out.append(Candidate(t, b, 4096, 2, 1, 1, e))
-        out.append(Candidate(t, b, 4096, 2, 4, -1, e, 0))
-        out.append(Candidate(t, b, 4096, 2, 4, 3, e, 0))
+    for t, b in itertools.product(tiles, blocks):
+        # a work item holds every species of a tile when they fit
+        chunk = 8192 if t[0] * t[1] * t[2] > 256 else 4096
+        for e in sort_every:
+            out.append(Candidate(t, b, chunk, 2, 4, -1, e, 0))
+        out.append(Candidate(t, b, chunk, 2, 4, 3, max(sort_every), 0))
+        out.append(Candidate(t, b, chunk, 2, 1, 2, max(sort_every), 0))
     return out
 
 

@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <map>
 #include <string>
 #include <vector>
@@ -94,7 +95,7 @@ struct pic_ctx {
     long long total_cells = 0;
     int *derr = nullptr;
     size_t lds_field_bytes = 0, lds_bytes = 0;
-    int margin = 0;                 // cells staged around each tile
+    int margin[3] = {0, 0, 0};      // cells staged around each tile, per axis
     int jrow = 0;                   // padded row length of the LDS current tile (0 = none)
     int frow = 0;                   // padded row length of the LDS field tile (0 = none)
     // species
@@ -355,7 +356,7 @@ KParams make_params(pic_ctx *c, const pic_fields *f, int nsp) {
     k.queue = c->queue;
     k.lds_field_bytes = (int)c->lds_field_bytes;
     k.lane_stride = c->tun.lane_stride;
-    k.margin = c->margin;
+    for (int d = 0; d < 3; ++d) k.margin[d] = c->margin[d];
     k.jrow = c->jrow;
     k.frow = c->frow;
     k.strag_count = c->strag_count;
@@ -695,7 +696,8 @@ pic_status pic_init(pic_ctx **out, const pic_box_desc *boxes, int32_t nboxes, pi
         for (int i = 0; i < nboxes; ++i) n3 += boxes[i].dim == 3;
         c->dims = n3 == nboxes ? 3 : (n3 == 0 ? 2 : 0);
     }
-    // LDS layout: a 1-cell margin around every tile when it fits, and rows
+    // LDS layout: a 1-cell margin around every tile (on the axes where it
+    // fits), and rows
     // padded (t.pad) so that a wave's lanes, which sit on a block of tile
     // rows, hit distinct LDS banks.
     int tx = 0;
@@ -709,9 +711,9 @@ pic_status pic_init(pic_ctx **out, const pic_box_desc *boxes, int32_t nboxes, pi
         while (!((row % per_pass) % tx == 0 && ((row % per_pass) / tx) % 2 == 1)) ++row;
         return row <= 2 * need ? row : 0;
     };
-    // LDS bytes of the field (F) or current (J) stage for a margin and a
-    // padded row length (0 = unpadded), max over the boxes.
-    auto stage_bytes = [&](bool field, int mg, int row) {
+    // LDS bytes of the field (F) or current (J) stage for a margin per axis
+    // and a padded row length (0 = unpadded), max over the boxes.
+    auto stage_bytes = [&](bool field, const int *mg, int row) {
         size_t mx = 0;
         for (int i = 0; i < nboxes; ++i) {
             const pic_box_desc &b = boxes[i];
@@ -719,7 +721,7 @@ pic_status pic_init(pic_ctx **out, const pic_box_desc *boxes, int32_t nboxes, pi
             size_t by = field ? 6 * fb : 3 * 8;   // the current tile is FP64 in both forms
             for (int k = 0; k < 3; ++k) {
                 if (b.dim == 2 && k == 1) continue;
-                size_t w = (size_t)(std::min(b.tile[k], b.n[k]) + lo + hi + 2 * mg);
+                size_t w = (size_t)(std::min(b.tile[k], b.n[k]) + lo + hi + 2 * mg[k]);
                 if (k == 0 && row > 0) w = std::max(w, (size_t)row);
                 by *= w;
             }
@@ -728,34 +730,48 @@ pic_status pic_init(pic_ctx **out, const pic_box_desc *boxes, int32_t nboxes, pi
         return field ? (mx + 15) / 16 * 16 : mx;
     };
     const int fpass = fb == 4 ? 64 : 32;
-    auto layout = [&](int mg, bool padf, bool padj, int &frow, int &jrow) {
-        frow = padf ? pad_row(tx + halo_gl(o) + halo_gh(o) + 2 * mg, fpass) : 0;
-        jrow = padj ? pad_row(tx + halo_jl(o) + halo_jh(o) + 2 * mg, 32) : 0;
+    auto layout = [&](const int *mg, bool padf, bool padj, int &frow, int &jrow) {
+        frow = padf ? pad_row(tx + halo_gl(o) + halo_gh(o) + 2 * mg[0], fpass) : 0;
+        jrow = padj ? pad_row(tx + halo_jl(o) + halo_jh(o) + 2 * mg[0], 32) : 0;
         return stage_bytes(true, mg, frow) + stage_bytes(false, mg, jrow);
     };
     {
         const size_t cap = (size_t)LDS_BYTES_MAX;
         int fr = 0, jr = 0;
-        c->margin = layout(1, false, false, fr, jr) <= cap ? 1 : 0;
+        // Margin axes are given up widest tile edge first (a particle leaves
+        // a wide tile through that axis least often).
+        int ext[3] = {0, 0, 0}, drop[3] = {0, 1, 2};
+        for (int i = 0; i < nboxes; ++i)
+            for (int k = 0; k < 3; ++k) ext[k] = std::max(ext[k], std::min(boxes[i].tile[k], boxes[i].n[k]));
+        std::stable_sort(drop, drop + 3, [&](int a, int b) { return ext[a] > ext[b]; });
+        int mg[3] = {1, 1, 1};
+        for (int i = 0; i < 3 && layout(mg, false, false, fr, jr) > cap; ++i) mg[drop[i]] = 0;
         bool padf = false, padj = false;
         if (t.pad >= 0) {
             // pad 0: current rows; 1: field rows, then current rows, each
-            // where it fits; 2: both, dropping the margin if need be
-            padj = layout(c->margin, false, true, fr, jr) <= cap && jr > 0;
+            // where it fits; 2: both, giving up margin axes if need be
+            padj = layout(mg, false, true, fr, jr) <= cap && jr > 0;
             if (t.pad >= 1) {
-                if (layout(c->margin, true, padj, fr, jr) <= cap && fr > 0) padf = true;
-                else if (layout(c->margin, true, false, fr, jr) <= cap && fr > 0) { padf = true; padj = false; }
-                if (t.pad == 2 && !(padf && padj) && c->margin == 1 &&
-                    layout(0, true, true, fr, jr) <= cap && fr > 0 && jr > 0) {
-                    c->margin = 0;
-                    padf = padj = true;
+                if (layout(mg, true, padj, fr, jr) <= cap && fr > 0) padf = true;
+                else if (layout(mg, true, false, fr, jr) <= cap && fr > 0) { padf = true; padj = false; }
+                if (t.pad == 2 && !(padf && padj)) {
+                    int m2[3] = {mg[0], mg[1], mg[2]};
+                    for (int i = 0; i < 3; ++i) {
+                        m2[drop[i]] = 0;
+                        if (layout(m2, true, true, fr, jr) <= cap && fr > 0 && jr > 0) {
+                            for (int k = 0; k < 3; ++k) mg[k] = m2[k];
+                            padf = padj = true;
+                            break;
+                        }
+                    }
                 }
             }
         }
-        c->lds_bytes = layout(c->margin, padf, padj, fr, jr);
+        c->lds_bytes = layout(mg, padf, padj, fr, jr);
         c->frow = fr;
         c->jrow = jr;
-        c->lds_field_bytes = stage_bytes(true, c->margin, fr);
+        for (int k = 0; k < 3; ++k) c->margin[k] = mg[k];
+        c->lds_field_bytes = stage_bytes(true, mg, fr);
     }
     if (t.kernel != PIC_KERNEL_DIRECT && c->lds_bytes > (size_t)LDS_BYTES_MAX) {
         delete c;

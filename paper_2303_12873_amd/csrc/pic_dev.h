@@ -78,7 +78,7 @@ struct KParams {
     int *queue;
     int lds_field_bytes;      // offset of the J region in dynamic LDS
     int lane_stride;          // lane -> particle stride inside a work item
-    int margin;               // cells staged around each tile (0 or 1)
+    int margin[3];            // cells staged around each tile per axis (0 or 1)
     int jrow;                 // minimum row length of the LDS current tile
     int frow;                 // minimum row length of the LDS field tile
     int *strag_count;         // per species: entries in its straggler list

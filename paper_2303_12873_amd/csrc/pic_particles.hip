@@ -433,17 +433,17 @@ __device__ __forceinline__ void deposit(const JA &ja, const int c0[3], const R f
 
 // ------------------------------------------------------------ one particle
 
-// A tile's cells [t0, t0 + te) plus the staged margin of `mg` cells, so a
+// A tile's cells [t0, t0 + te) plus the staged margin of mg[d] cells per axis, so a
 // particle that drifted up to mg cells out of its tile since the last sort
 // still gathers and deposits through LDS.  In 2D the y range is the single
 // cell 0 and always holds.
 struct Tile {
     int t0[3], te[3];
-    int mg;
+    int mg[3];
     __device__ inline bool holds(const int c[3]) const {
-        return c[0] >= t0[0] - mg && c[0] < t0[0] + te[0] + mg &&
-               c[1] >= t0[1] - mg && c[1] < t0[1] + te[1] + mg &&
-               c[2] >= t0[2] - mg && c[2] < t0[2] + te[2] + mg;
+        return c[0] >= t0[0] - mg[0] && c[0] < t0[0] + te[0] + mg[0] &&
+               c[1] >= t0[1] - mg[1] && c[1] < t0[1] + te[1] + mg[1] &&
+               c[2] >= t0[2] - mg[2] && c[2] < t0[2] + te[2] + mg[2];
     }
 };
 
@@ -1109,26 +1109,32 @@ __device__ __forceinline__ void process_item(const KParams &prm, const Item &it,
     LdsJ<A> lj;
     // field region: cells [t0 - GL, t0 + te + GH) per active axis
     lf.base = (const FT *)smem;
-    tile.mg = prm.margin;
-    const int GL = H::GL + tile.mg, GW = H::GL + H::GH + 2 * tile.mg;
+    int GL[3], GW[3], JL[3], JW[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        tile.mg[d] = prm.margin[d];
+        GL[d] = H::GL + tile.mg[d];
+        GW[d] = H::GL + H::GH + 2 * tile.mg[d];
+        JL[d] = H::JL + tile.mg[d];
+        JW[d] = H::JL + H::JH + 2 * tile.mg[d];
+    }
     // Row length of the LDS field tile: padded (prm.frow) like the current
     // tile's; only the first W entries of a row are staged.
-    const int W = tile.te[0] + GW;
-    lf.o0 = tile.t0[0] - GL; lf.L0 = max(W, prm.frow);
-    lf.o2 = tile.t0[2] - GL;
-    int L2 = tile.te[2] + GW;
-    if (DIM == 3) { lf.o1 = tile.t0[1] - GL; lf.L1 = tile.te[1] + GW; }
+    const int W = tile.te[0] + GW[0];
+    lf.o0 = tile.t0[0] - GL[0]; lf.L0 = max(W, prm.frow);
+    lf.o2 = tile.t0[2] - GL[2];
+    int L2 = tile.te[2] + GW[2];
+    if (DIM == 3) { lf.o1 = tile.t0[1] - GL[1]; lf.L1 = tile.te[1] + GW[1]; }
     else { lf.o1 = 0; lf.L1 = 1; }
     lf.L012 = lf.L0 * lf.L1 * L2;
     // current region: nodes [t0 - JL, t0 + te + JH) per active axis
     lj.base = (A *)(smem + prm.lds_field_bytes);
-    const int JL = H::JL + tile.mg, JW = H::JL + H::JH + 2 * tile.mg;
     // Row length of the LDS current tile: padded (prm.jrow, from the host)
     // so that a wave's lanes on an 8-wide block of rows hit distinct banks.
-    lj.o0 = tile.t0[0] - JL; lj.M0 = max(tile.te[0] + JW, prm.jrow);
-    lj.o2 = tile.t0[2] - JL;
-    int M2 = tile.te[2] + JW;
-    if (DIM == 3) { lj.o1 = tile.t0[1] - JL; lj.M1 = tile.te[1] + JW; }
+    lj.o0 = tile.t0[0] - JL[0]; lj.M0 = max(tile.te[0] + JW[0], prm.jrow);
+    lj.o2 = tile.t0[2] - JL[2];
+    int M2 = tile.te[2] + JW[2];
+    if (DIM == 3) { lj.o1 = tile.t0[1] - JL[1]; lj.M1 = tile.te[1] + JW[1]; }
     else { lj.o1 = 0; lj.M1 = 1; }
     lj.M012 = lj.M0 * lj.M1 * M2;
 

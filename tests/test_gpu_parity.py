@@ -467,3 +467,23 @@ def test_padded_lds_rows(prec, tol, pad):
     E, B, J = run.fields_np()
     assert rel_l2(J, Jo) <= tol and rel_l2(E, Eo) <= tol, (rel_l2(J, Jo), rel_l2(E, Eo))
     run.free()
+
+
+@pytest.mark.parametrize("prec,tol", ((pic.PIC_FP64, TOL64), (pic.PIC_FP32_SPLIT, TOL32)))
+def test_margin_on_some_axes(prec, tol):
+    """Order-3 16x8x4 tiles: the staged margin does not fit on every axis,
+    so it is given up along x only; hot plasma drifts across tile faces in
+    every direction (LDS path inside the margin, global path beyond)."""
+    wl = pi.uniform_box((32, 16, 12), 3, 0.05, 0.3, 3, 2300, "cpu", tile=(16, 8, 4),
+                        fields="fourier", species=("e", "i"))
+    Eo, Bo, Jo, sps = _oracle_steps(wl, 4)
+    run = GpuRun(wl, prec, kernel=pic.PIC_KERNEL_BATCHED, lane_stride=4, cell_order=-1,
+                 chunk=8192, block=512)
+    run.sort()
+    for _ in range(4):
+        run.particles()
+        pic.pic_fdtd_step(run.ctx, run.f)
+    run.check()
+    E, B, J = run.fields_np()
+    assert rel_l2(J, Jo) <= tol and rel_l2(E, Eo) <= tol, (rel_l2(J, Jo), rel_l2(E, Eo))
+    run.free()
