@@ -51,9 +51,9 @@ def kernel_source_sha():
     return h.hexdigest()
 
 
-def launch_config(tile, block, stride, cell_order, pad):
+def launch_config(tile, block, stride, cell_order, pad, margin):
     return (f"tile={tuple(tile)} block={block} lane_stride={stride} cell_order={cell_order} "
-            f"pad={pad}")
+            f"pad={pad} margin={margin}")
 
 
 def measured_traffic(workload, config):
@@ -97,7 +97,7 @@ def build_workload(name, device):
 
 
 def run_form(wl, precision, kernel, steps, warmup, sort_every, tile, block, chunk, wg, stride,
-             cell_order=0, pad=0):
+             cell_order=0, pad=0, margin=0):
     import torch
     import paper_2303_12873_amd as pic
     import pic_inputs as pi
@@ -108,7 +108,7 @@ def run_form(wl, precision, kernel, steps, warmup, sort_every, tile, block, chun
     with torch.cuda.stream(stream):
         ctx = pic.pic_init(boxes, precision, stream=stream.cuda_stream, kernel=kernel,
                            block=block, chunk=chunk, wg_per_cu=wg, lane_stride=stride,
-                           cell_order=cell_order, pad=pad)
+                           cell_order=cell_order, pad=pad, margin=margin)
         f = pic.make_fields(boxes, wl.E, wl.B, precision)
         sp = [pic.make_species(p, precision) for p in wl.species]
     torch.cuda.synchronize()
@@ -217,6 +217,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cell-order", type=int, default=0,
                     help="FP32 within-tile order without the tuner (-1, 1, 2; 0 = library default)")
+    ap.add_argument("--margin", type=int, default=0,
+                    help="FP32 staged margin without the tuner (0 where it fits, -1 none)")
     ap.add_argument("--pad", type=int, default=0,
                     help="FP32 LDS row padding without the tuner (-1, 0, 1, 2)")
     ap.add_argument("--no-tune", action="store_true",
@@ -244,7 +246,9 @@ def main():
         f"{sum(b.ncells for b in wl.boxes)} cells, generated in {time.time() - t0:.1f}s")
 
     cell_order = args.cell_order
-    tuned = None
+    tuned = tuned64 = None
+    args.sort_every64 = args.sort_every
+    args.margin64 = 0
     if not args.no_tune:
         from paper_2303_12873_amd.autotune import tune
         # Tune on the workload itself (a half-size sample ranked the
@@ -259,19 +263,35 @@ def main():
             args.wg_per_cu, args.stride, cell_order = best.wg_per_cu, best.lane_stride, best.cell_order
             args.sort_every = best.sort_every
             args.pad = best.pad
+            args.margin = best.margin
             tuned = {"picked": best.key(), "candidates": len(table),
                      "seconds": round(time.time() - t1, 1)}
         log(f"  autotuner: {tuned}")
+        if not args.no_fp64:
+            # the plain FP64 form gets the same search over its own space
+            # (non-persistent tiled kernel, 512 threads)
+            t1 = time.time()
+            best64, table64 = tune(wl, pic.PIC_FP64, budget_s=args.tune_budget, cache=None,
+                                   log=log, kernel=pic.PIC_KERNEL_TILED)
+            torch.cuda.empty_cache()
+            if best64 is not None:
+                args.tile64, args.block64 = tuple(best64.tile), best64.block
+                args.stride64, args.sort_every64 = best64.lane_stride, best64.sort_every
+                args.margin64 = best64.margin
+                tuned64 = {"picked": best64.key(), "candidates": len(table64),
+                           "seconds": round(time.time() - t1, 1)}
+            log(f"  autotuner (FP64 plain): {tuned64}")
     log("FP32 split + batched form")
     r32 = run_form(wl, pic.PIC_FP32_SPLIT, pic.PIC_KERNEL_BATCHED, args.steps, args.warmup,
                    args.sort_every, args.tile32, args.block, args.chunk, args.wg_per_cu, args.stride,
-                   cell_order, args.pad)
+                   cell_order, args.pad, args.margin)
     log(f"  {r32}")
     r64 = None
     if not args.no_fp64:
         log("FP64 plain (tiled) form")
-        r64 = run_form(wl, pic.PIC_FP64, pic.PIC_KERNEL_TILED, max(3, args.steps // 4), 1,
-                       args.sort_every, args.tile64, args.block64, 0, 0, args.stride64)
+        r64 = run_form(wl, pic.PIC_FP64, pic.PIC_KERNEL_TILED, args.steps, args.warmup,
+                       args.sort_every64, args.tile64, args.block64, 0, 0, args.stride64,
+                       -1, 0, args.margin64)
         log(f"  {r64}")
 
     value = r32["np"] * 1e3 / r32["ms_step"]
@@ -285,7 +305,7 @@ def main():
     tfl = flops_launch / t_adv / 1e12
     f_hbm, f_alu = gbs / PEAK_HBM_GBS, tfl / PEAK_VALU_TFLOPS
     traffic = measured_traffic(wl.name, launch_config(args.tile32, args.block, args.stride,
-                                                       cell_order, args.pad))
+                                                       cell_order, args.pad, args.margin))
     if f_alu >= f_hbm:
         roof = {"bound": "alu", "achieved": round(tfl, 3), "peak": PEAK_VALU_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(f_alu, 4), "traffic": traffic,
@@ -307,7 +327,8 @@ def main():
                    "form": "fp32_split_batched_graph", "sort_every": args.sort_every,
                    "tile": list(args.tile32), "block": args.block, "chunk": args.chunk,
                    "wg_per_cu": args.wg_per_cu, "lane_stride": args.stride,
-                   "cell_order": cell_order, "pad": args.pad, "autotuned": tuned},
+                   "cell_order": cell_order, "pad": args.pad, "margin": args.margin,
+                   "autotuned": tuned},
         "roofline": roof,
         "breakdown_ms": {"advance": r32["ms_advance"], "sort": r32["ms_sort"],
                          "fdtd": r32["ms_fdtd"]},
@@ -317,7 +338,9 @@ def main():
         out["fp64_plain"] = {"value": v64, "ms_per_step": r64["ms_step"],
                              "breakdown_ms": {"advance": r64["ms_advance"], "sort": r64["ms_sort"],
                                               "fdtd": r64["ms_fdtd"]},
-                             "tile": list(args.tile64)}
+                             "tile": list(args.tile64), "block": args.block64,
+                             "lane_stride": args.stride64, "sort_every": args.sort_every64,
+                             "margin": args.margin64, "autotuned": tuned64}
         out["speedup_fp32_batched_vs_fp64_plain"] = value / v64
     if not args.no_cpu:
         log("oracle CPU baseline")

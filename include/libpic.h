@@ -132,6 +132,10 @@ typedef struct {
                             over waves; -1 = in a row; 0 = default: 1 for a
                             species with at least 6 particles per cell of its
                             box on average, else -1. */
+    int32_t margin;      /* TILED/BATCHED: 0 = stage the 1-cell margin on the
+                            axes where it fits (default); -1 = no margin
+                            (particles out of their tile since the sort take
+                            the global path; smaller LDS stage). */
 } pic_tuning;
 
 typedef struct {

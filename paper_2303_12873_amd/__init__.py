@@ -40,7 +40,7 @@ class pic_box_desc(C.Structure):
 class pic_tuning(C.Structure):
     _fields_ = [("kernel", C.c_int32), ("block", C.c_int32), ("chunk", C.c_int32),
                 ("wg_per_cu", C.c_int32), ("lane_stride", C.c_int32), ("pad", C.c_int32),
-                ("cell_order", C.c_int32), ("quad_spread", C.c_int32)]
+                ("cell_order", C.c_int32), ("quad_spread", C.c_int32), ("margin", C.c_int32)]
 
 
 class pic_fields(C.Structure):
@@ -212,7 +212,7 @@ def _ptr_array(ts):
 
 def pic_init(boxes, precision: int, stream=None, kernel: Optional[int] = None, block: int = 0,
              chunk: int = 0, wg_per_cu: int = 0, lane_stride: int = 0, pad: int = 0,
-             cell_order: int = 0, quad_spread: int = 0):
+             cell_order: int = 0, quad_spread: int = 0, margin: int = 0):
     """boxes: objects with dim, n, dx, dt, order, tile (``pic_inputs.Box``).
     Returns an opaque context handle (int)."""
     descs = (pic_box_desc * len(boxes))()
@@ -229,7 +229,8 @@ def pic_init(boxes, precision: int, stream=None, kernel: Optional[int] = None, b
         d.cell_base = base
         base += b.ncells
     tun = None
-    if kernel is not None or block or chunk or wg_per_cu or lane_stride or pad or cell_order or quad_spread:
+    if (kernel is not None or block or chunk or wg_per_cu or lane_stride or pad or cell_order
+            or quad_spread or margin):
         tun = pic_tuning()
         tun.kernel = (PIC_KERNEL_TILED if precision == PIC_FP64 else PIC_KERNEL_BATCHED) \
             if kernel is None else kernel
@@ -238,6 +239,7 @@ def pic_init(boxes, precision: int, stream=None, kernel: Optional[int] = None, b
         tun.pad = pad
         tun.cell_order = cell_order
         tun.quad_spread = quad_spread
+        tun.margin = margin
     if stream is None:
         stream = torch.cuda.current_stream().cuda_stream
     h = C.c_void_p()

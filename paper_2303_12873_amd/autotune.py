@@ -36,10 +36,11 @@ class Candidate:
     cell_order: int = 2
     sort_every: int = 8
     pad: int = 0
+    margin: int = 0
 
     def key(self):
         return (f"t{self.tile}-b{self.block}-c{self.chunk}-w{self.wg_per_cu}-s{self.lane_stride}"
-                f"-o{self.cell_order}-e{self.sort_every}-p{self.pad}")
+                f"-o{self.cell_order}-e{self.sort_every}-p{self.pad}-m{self.margin}")
 
 
 def default_space(dim3: bool, precision=pic.PIC_FP32_SPLIT, sort_every=(8, 16)):
@@ -49,15 +50,19 @@ def default_space(dim3: bool, precision=pic.PIC_FP32_SPLIT, sort_every=(8, 16)):
     suit them, and sort intervals.  Field-row padding (pad 1, 2) never beat
     the current-row padding on the workloads measured and is left out."""
     tiles = [(8, 8, 4), (16, 8, 4), (8, 8, 8)] if dim3 else [(8, 1, 8), (16, 1, 16)]
-    blocks = [1024] if precision == pic.PIC_FP32_SPLIT else [512]
+    split = precision == pic.PIC_FP32_SPLIT
+    blocks = [1024] if split else [512]
+    e = max(sort_every)
     out = []
     for t, b in itertools.product(tiles, blocks):
         # a work item holds every species of a tile when they fit
         chunk = 8192 if t[0] * t[1] * t[2] > 256 else 4096
-        for e in sort_every:
-            out.append(Candidate(t, b, chunk, 2, 4, -1, e, 0))
-        out.append(Candidate(t, b, chunk, 2, 4, 3, max(sort_every), 0))
-        out.append(Candidate(t, b, chunk, 2, 1, 2, max(sort_every), 0))
+        out.append(Candidate(t, b, chunk, 2, 4, -1, e, 0, 0))
+        out.append(Candidate(t, b, chunk, 2, 4, -1, e, 0, -1))
+        if split:
+            out.append(Candidate(t, b, chunk, 2, 4, -1, min(sort_every), 0, 0))
+            out.append(Candidate(t, b, chunk, 2, 4, 3, e, 0, 0))
+            out.append(Candidate(t, b, chunk, 2, 1, 2, e, 0, 0))
     return out
 
 
@@ -75,13 +80,14 @@ def _retile(boxes, tile):
                    tuple(tile) if b.dim == 3 else (tile[0], 1, tile[2]), b.dx) for b in boxes]
 
 
-def _run(wl, precision, cand: Candidate, steps: int, stream, warm: int = 4):
+def _run(wl, precision, cand: Candidate, steps: int, stream, warm: int = 4,
+         kernel: int = pic.PIC_KERNEL_BATCHED):
     boxes = _retile(wl.boxes, cand.tile)
     with torch.cuda.stream(stream):
         ctx = pic.pic_init(boxes, precision, stream=stream.cuda_stream,
-                           kernel=pic.PIC_KERNEL_BATCHED, block=cand.block, chunk=cand.chunk,
+                           kernel=kernel, block=cand.block, chunk=cand.chunk,
                            wg_per_cu=cand.wg_per_cu, lane_stride=cand.lane_stride,
-                           cell_order=cand.cell_order, pad=cand.pad)
+                           cell_order=cand.cell_order, pad=cand.pad, margin=cand.margin)
         f = pic.make_fields(boxes, wl.E, wl.B, precision)
         sp = [pic.make_species(p, precision) for p in wl.species]
     try:
@@ -109,7 +115,7 @@ def _run(wl, precision, cand: Candidate, steps: int, stream, warm: int = 4):
 
 def tune(wl, precision=pic.PIC_FP32_SPLIT, space: Optional[List[Candidate]] = None,
          steps: Optional[int] = None, budget_s: float = 120.0,
-         cache: Optional[str] = DEFAULT_CACHE, log=print):
+         cache: Optional[str] = DEFAULT_CACHE, log=print, kernel: int = pic.PIC_KERNEL_BATCHED):
     """Returns (best Candidate, table of (key, ms or reason)).  Each candidate
     runs `steps` whole steps (default: the longest sort interval of the
     space, so every candidate's window holds its sort and the drift after
@@ -117,7 +123,7 @@ def tune(wl, precision=pic.PIC_FP32_SPLIT, space: Optional[List[Candidate]] = No
     dim3 = all(b.dim == 3 for b in wl.boxes)
     space = space or default_space(dim3, precision)
     steps = steps or max(c.sort_every for c in space)
-    wkey = f"{torch.cuda.get_device_name(0)}|{workload_key(wl, precision)}"
+    wkey = f"{torch.cuda.get_device_name(0)}|{workload_key(wl, precision)}|k{kernel}"
     if cache and os.path.exists(cache):
         try:
             db = json.load(open(cache))
@@ -138,7 +144,7 @@ def tune(wl, precision=pic.PIC_FP32_SPLIT, space: Optional[List[Candidate]] = No
             table.append((cand.key(), "skipped: budget"))
             continue
         try:
-            ms, E, J = _run(wl, precision, cand, steps, stream)
+            ms, E, J = _run(wl, precision, cand, steps, stream, kernel=kernel)
         except pic.PicError as e:
             table.append((cand.key(), f"rejected: {e}"))
             continue

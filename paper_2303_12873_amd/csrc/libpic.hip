@@ -628,6 +628,7 @@ pic_status pic_init(pic_ctx **out, const pic_box_desc *boxes, int32_t nboxes, pi
     t.pad = 0;
     t.cell_order = 0;
     t.quad_spread = 0;
+    t.margin = 0;
     if (tuning) {
         t.kernel = tuning->kernel;
         if (tuning->block) t.block = tuning->block;
@@ -637,6 +638,7 @@ pic_status pic_init(pic_ctx **out, const pic_box_desc *boxes, int32_t nboxes, pi
         t.pad = tuning->pad;
         t.cell_order = tuning->cell_order;
         t.quad_spread = tuning->quad_spread;
+        t.margin = tuning->margin;
     }
     if (t.kernel < 0 || t.kernel > 2) return fail(PIC_ERR_ARG, "bad kernel form");
     const int max_block = prec == PIC_FP64 ? 512 : 1024;
@@ -648,6 +650,7 @@ pic_status pic_init(pic_ctx **out, const pic_box_desc *boxes, int32_t nboxes, pi
     if (t.cell_order < -1 || t.cell_order > 3) return fail(PIC_ERR_ARG, "cell_order must be -1..3");
     if (t.pad < -1 || t.pad > 2) return fail(PIC_ERR_ARG, "pad must be -1..2");
     if (t.quad_spread < -1 || t.quad_spread > 1) return fail(PIC_ERR_ARG, "quad_spread must be -1..1");
+    if (t.margin < -1 || t.margin > 0) return fail(PIC_ERR_ARG, "margin must be -1 or 0");
     t.cell_order = t.cell_order == 0 ? (t.kernel == PIC_KERNEL_BATCHED ? 2 : 0) : std::max(t.cell_order, 0);
 
     pic_ctx *c = new pic_ctx();
@@ -744,7 +747,8 @@ pic_status pic_init(pic_ctx **out, const pic_box_desc *boxes, int32_t nboxes, pi
         for (int i = 0; i < nboxes; ++i)
             for (int k = 0; k < 3; ++k) ext[k] = std::max(ext[k], std::min(boxes[i].tile[k], boxes[i].n[k]));
         std::stable_sort(drop, drop + 3, [&](int a, int b) { return ext[a] > ext[b]; });
-        int mg[3] = {1, 1, 1};
+        const int m0 = t.margin < 0 ? 0 : 1;
+        int mg[3] = {m0, m0, m0};
         for (int i = 0; i < 3 && layout(mg, false, false, fr, jr) > cap; ++i) mg[drop[i]] = 0;
         bool padf = false, padj = false;
         if (t.pad >= 0) {

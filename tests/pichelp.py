@@ -43,13 +43,14 @@ class GpuRun:
     """One box (or several) and its species on the GPU, FP64 or split form."""
 
     def __init__(self, wl, precision, kernel=None, block=0, chunk=0, wg_per_cu=0, stream=None,
-                 lane_stride=0, cell_order=0, quad_spread=0, pad=0):
+                 lane_stride=0, cell_order=0, quad_spread=0, pad=0, margin=0):
         ensure_built()
         self.wl = wl
         self.prec = precision
         self.ctx = pic.pic_init(wl.boxes, precision, stream=stream, kernel=kernel, block=block,
                                 chunk=chunk, wg_per_cu=wg_per_cu, lane_stride=lane_stride,
-                                cell_order=cell_order, quad_spread=quad_spread, pad=pad)
+                                cell_order=cell_order, quad_spread=quad_spread, pad=pad,
+                                margin=margin)
         self.f = pic.make_fields(wl.boxes, wl.E, wl.B, precision)
         self.sp = [pic.make_species(p, precision) for p in wl.species]
         self.kernel = kernel if kernel is not None else (

@@ -470,7 +470,8 @@ def test_padded_lds_rows(prec, tol, pad):
 
 
 @pytest.mark.parametrize("prec,tol", ((pic.PIC_FP64, TOL64), (pic.PIC_FP32_SPLIT, TOL32)))
-def test_margin_on_some_axes(prec, tol):
+@pytest.mark.parametrize("margin", (0, -1))
+def test_margin_on_some_axes(prec, tol, margin):
     """Order-3 16x8x4 tiles: the staged margin does not fit on every axis,
     so it is given up along x only; hot plasma drifts across tile faces in
     every direction (LDS path inside the margin, global path beyond)."""
@@ -478,7 +479,7 @@ def test_margin_on_some_axes(prec, tol):
                         fields="fourier", species=("e", "i"))
     Eo, Bo, Jo, sps = _oracle_steps(wl, 4)
     run = GpuRun(wl, prec, kernel=pic.PIC_KERNEL_BATCHED, lane_stride=4, cell_order=-1,
-                 chunk=8192, block=512)
+                 chunk=8192, block=512, margin=margin)
     run.sort()
     for _ in range(4):
         run.particles()
