@@ -716,17 +716,24 @@ pic_status pic_init(pic_ctx **out, const pic_box_desc *boxes, int32_t nboxes, pi
     };
     // LDS bytes of the field (F) or current (J) stage for a margin per axis
     // and a padded row length (0 = unpadded), max over the boxes.
+    // (each field component spans only its own stencil's nodes, by stagger)
     auto stage_bytes = [&](bool field, const int *mg, int row) {
         size_t mx = 0;
         for (int i = 0; i < nboxes; ++i) {
             const pic_box_desc &b = boxes[i];
-            const int lo = field ? halo_gl(o) : halo_jl(o), hi = field ? halo_gh(o) : halo_jh(o);
-            size_t by = field ? 6 * fb : 3 * 8;   // the current tile is FP64 in both forms
-            for (int k = 0; k < 3; ++k) {
-                if (b.dim == 2 && k == 1) continue;
-                size_t w = (size_t)(std::min(b.tile[k], b.n[k]) + lo + hi + 2 * mg[k]);
-                if (k == 0 && row > 0) w = std::max(w, (size_t)row);
-                by *= w;
+            size_t by = 0;
+            for (int c = 0; c < (field ? 6 : 3); ++c) {
+                size_t n = field ? fb : 8;         // the current tile is FP64 in both forms
+                for (int k = 0; k < 3; ++k) {
+                    if (b.dim == 2 && k == 1) continue;
+                    const int st = comp_stagger(c, k);
+                    const int lo = field ? gather_lo(o, st) : halo_jl(o);
+                    const int hi = field ? gather_hi(o, st) : halo_jh(o);
+                    size_t w = (size_t)(std::min(b.tile[k], b.n[k]) + lo + hi + 2 * mg[k]);
+                    if (k == 0 && row > 0) w = std::max(w, (size_t)row);
+                    n *= w;
+                }
+                by += n;
             }
             mx = std::max(mx, by);
         }

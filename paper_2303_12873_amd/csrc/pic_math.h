@@ -175,6 +175,19 @@ template <> struct Halo<1> { static constexpr int GL = 1, GH = 1, JL = 1, JH = 2
 template <> struct Halo<2> { static constexpr int GL = 1, GH = 2, JL = 2, JH = 3; };
 template <> struct Halo<3> { static constexpr int GL = 2, GH = 2, JL = 2, JH = 3; };
 
+// Gather node range of one field component along one axis, by its stagger
+// st (0: integer points, 1: half-shifted): [c - lo, c + hi].
+__host__ __device__ constexpr int gather_lo(int order, int st) {
+    return order == 1 ? st : (order == 2 ? 1 : 1 + st);
+}
+__host__ __device__ constexpr int gather_hi(int order, int st) {
+    return order == 1 ? 1 : (order == 2 ? 2 - st : 2);
+}
+// Stagger of field component comp (0..2: E, 3..5: B) along axis d.
+__host__ __device__ constexpr int comp_stagger(int comp, int d) {
+    return comp < 3 ? (comp == d ? 1 : 0) : (comp - 3 == d ? 0 : 1);
+}
+
 // ---------------------------------------------------------------- push
 
 // Relativistic Boris rotation with h = q dt / (2 m).

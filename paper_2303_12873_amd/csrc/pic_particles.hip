@@ -115,17 +115,20 @@ template <typename T> struct GlobalField {
     }
 };
 
+// The staged E/B tile: each component holds only the nodes its own gather
+// stencil can reach (its extent differs by stagger), at its own offset.
 template <typename T> struct LdsField {
     static constexpr bool LDS = true;
     const T *base;
-    int o0, o1, o2, L0, L1, L012;
+    int off[6], o0[6], o1[6], o2[6], L0[6], L01[6];
     __device__ inline T load(int comp, int i, int j, int k) const {
-        return base[comp * L012 + (i - o0) + L0 * ((j - o1) + L1 * (k - o2))];
+        return *at(comp, i, j, k);
     }
     // Address of node (i, j, k) of a component; neighbours are reached by
-    // adding the uniform row (L0) and plane (L0 L1) strides.
+    // adding the component's row (L0) and plane (L01) strides.
     __device__ inline const T *at(int comp, int i, int j, int k) const {
-        return base + comp * L012 + (i - o0) + L0 * ((j - o1) + L1 * (k - o2));
+        return base + off[comp] + (i - o0[comp]) + L0[comp] * (j - o1[comp]) +
+               L01[comp] * (k - o2[comp]);
     }
 };
 
@@ -166,7 +169,7 @@ __device__ __forceinline__ R interp(const FA &fa, int comp, const GWin<O, R> &wx
     R sum = R(0);
     if constexpr (FA::LDS) {
         const auto *p0 = fa.at(comp, wx.base, wy.base, wz.base);
-        const int rs = fa.L0, ps = fa.L0 * fa.L1;
+        const int rs = fa.L0[comp], ps = fa.L01[comp];
         if (DIM == 3) {
 #pragma unroll
             for (int kk = 0; kk <= O; ++kk) {
@@ -1109,24 +1112,40 @@ __device__ __forceinline__ void process_item(const KParams &prm, const Item &it,
     LdsJ<A> lj;
     // field region: cells [t0 - GL, t0 + te + GH) per active axis
     lf.base = (const FT *)smem;
-    int GL[3], GW[3], JL[3], JW[3];
+    int JL[3], JW[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         tile.mg[d] = prm.margin[d];
-        GL[d] = H::GL + tile.mg[d];
-        GW[d] = H::GL + H::GH + 2 * tile.mg[d];
         JL[d] = H::JL + tile.mg[d];
         JW[d] = H::JL + H::JH + 2 * tile.mg[d];
     }
-    // Row length of the LDS field tile: padded (prm.frow) like the current
-    // tile's; only the first W entries of a row are staged.
-    const int W = tile.te[0] + GW[0];
-    lf.o0 = tile.t0[0] - GL[0]; lf.L0 = max(W, prm.frow);
-    lf.o2 = tile.t0[2] - GL[2];
-    int L2 = tile.te[2] + GW[2];
-    if (DIM == 3) { lf.o1 = tile.t0[1] - GL[1]; lf.L1 = tile.te[1] + GW[1]; }
-    else { lf.o1 = 0; lf.L1 = 1; }
-    lf.L012 = lf.L0 * lf.L1 * L2;
+    // Field components: nodes [t0 - lo - mg, t0 + te + hi + mg) per active
+    // axis, lo/hi by the component's stagger.  Rows padded to prm.frow
+    // (only the first W[c] entries of a row are staged).
+    int W[6], FL1[6], FL2[6];
+    {
+        int acc = 0;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+            int lo[3], w[3];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                const int st = comp_stagger(c, d);
+                lo[d] = gather_lo(O, st) + tile.mg[d];
+                w[d] = tile.te[d] + gather_lo(O, st) + gather_hi(O, st) + 2 * tile.mg[d];
+            }
+            W[c] = w[0];
+            lf.o0[c] = tile.t0[0] - lo[0];
+            lf.L0[c] = max(w[0], prm.frow);
+            lf.o2[c] = tile.t0[2] - lo[2];
+            FL2[c] = w[2];
+            if (DIM == 3) { lf.o1[c] = tile.t0[1] - lo[1]; FL1[c] = w[1]; }
+            else { lf.o1[c] = 0; FL1[c] = 1; }
+            lf.L01[c] = lf.L0[c] * FL1[c];
+            lf.off[c] = acc;
+            acc += lf.L01[c] * FL2[c];
+        }
+    }
     // current region: nodes [t0 - JL, t0 + te + JH) per active axis
     lj.base = (A *)(smem + prm.lds_field_bytes);
     // Row length of the LDS current tile: padded (prm.jrow, from the host)
@@ -1140,16 +1159,19 @@ __device__ __forceinline__ void process_item(const KParams &prm, const Item &it,
 
     const int tid = threadIdx.x, bs = blockDim.x;
     if (MODE & MODE_PUSH) {
-        FT *dst = (FT *)smem;
-        const int n = 6 * lf.L012;
-        RegionWalk w(tid, bs, lf.L0, lf.L1, L2);
-        for (int idx = tid; idx < n; idx += bs, w.next()) {
-            if (w.i >= W) continue;
-            int gi = lf.o0 + w.i, gj = lf.o1 + w.j, gk = lf.o2 + w.k;
-            if (any) { gi = wrap_index_any(gi, b.n[0]); gj = wrap_index_any(gj, b.n[1]); gk = wrap_index_any(gk, b.n[2]); }
-            else { gi = wrap_index(gi, b.n[0]); gj = wrap_index(gj, b.n[1]); gk = wrap_index(gk, b.n[2]); }
-            const FT *src = (const FT *)(w.c < 3 ? prm.f.E[w.c] : prm.f.B[w.c - 3]);
-            dst[idx] = src[b.cell_base + gi + (long long)b.n[0] * (gj + (long long)b.n[1] * gk)];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+            FT *dst = (FT *)smem + lf.off[c];
+            const FT *src = (const FT *)(c < 3 ? prm.f.E[c] : prm.f.B[c - 3]);
+            const int n = lf.L01[c] * FL2[c];
+            RegionWalk w(tid, bs, lf.L0[c], FL1[c], FL2[c]);
+            for (int idx = tid; idx < n; idx += bs, w.next()) {
+                if (w.i >= W[c]) continue;
+                int gi = lf.o0[c] + w.i, gj = lf.o1[c] + w.j, gk = lf.o2[c] + w.k;
+                if (any) { gi = wrap_index_any(gi, b.n[0]); gj = wrap_index_any(gj, b.n[1]); gk = wrap_index_any(gk, b.n[2]); }
+                else { gi = wrap_index(gi, b.n[0]); gj = wrap_index(gj, b.n[1]); gk = wrap_index(gk, b.n[2]); }
+                dst[idx] = src[b.cell_base + gi + (long long)b.n[0] * (gj + (long long)b.n[1] * gk)];
+            }
         }
     }
     if (MODE & MODE_DEPOSIT) {
