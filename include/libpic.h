@@ -101,12 +101,17 @@ typedef struct {
                             particle (l mod G)*stride + l/G, G = ceil(n/stride),
                             so lanes of one wave fall in distinct cells when
                             stride ~ particles per cell (1..64; 0 = 1) */
-    int32_t pad;         /* Row padding of the LDS tiles, so that a wave's
-                            lanes (a block of tile rows) hit distinct LDS
-                            banks.  0: current tile rows, when it fits;
-                            1: field tile rows, then current tile rows, each
-                            when it fits; 2: both, giving up margin axes if
-                            that is what makes both fit; -1: no padding */
+    int32_t pad;         /* Row padding of the LDS tiles, so that the lanes
+                            of one LDS pass (32 for a 4-byte access, 16 for
+                            an 8-byte one; a wave sits on a block of tile
+                            rows) hit distinct banks.  0: current tile rows,
+                            when it fits; 1: field tile rows, then current
+                            tile rows, each when it fits; 2: both, giving up
+                            margin axes if that is what makes both fit;
+                            -1: no padding.  With 16-wide tiles and padded
+                            FP32 field rows the library also swaps lane bits
+                            4 and 5 of each wave's slots (results are the
+                            same; only the lane of a particle changes) */
     int32_t cell_order;  /* Order of the particles inside a tile after
                             pic_sort_tiles.  -1: previous order (tile id
                             only).  1: by class (lx+ly+lz) mod 4 of the

@@ -98,6 +98,7 @@ struct pic_ctx {
     int margin[3] = {0, 0, 0};      // cells staged around each tile, per axis
     int jrow = 0;                   // padded row length of the LDS current tile (0 = none)
     int frow = 0;                   // padded row length of the LDS field tile (0 = none)
+    int lane_swz = 0;               // swap lane bits 4 and 5 (16-wide rows, padded FP32 field)
     // species
     std::vector<Slot> slots;
     std::vector<DevSpecies> hsp;    // last uploaded table
@@ -359,6 +360,7 @@ KParams make_params(pic_ctx *c, const pic_fields *f, int nsp) {
     for (int d = 0; d < 3; ++d) k.margin[d] = c->margin[d];
     k.jrow = c->jrow;
     k.frow = c->frow;
+    k.lane_swz = c->lane_swz;
     k.strag_count = c->strag_count;
     k.box_sp_off = c->dbox_sp_off;
     k.box_sp = c->dbox_sp;
@@ -705,13 +707,22 @@ pic_status pic_init(pic_ctx **out, const pic_box_desc *boxes, int32_t nboxes, pi
     // rows, hit distinct LDS banks.
     int tx = 0;
     for (int i = 0; i < nboxes; ++i) tx = std::max(tx, std::min(boxes[i].tile[0], boxes[i].n[0]));
-    // Smallest row >= need that is an odd multiple of tx modulo the row
-    // elements one pass over the 64 banks holds (64 FP32, 32 FP64); 0 if
-    // none within 2x need.
-    auto pad_row = [&](int need, int per_pass) {
-        if (tx <= 0 || tx >= per_pass || per_pass % tx) return 0;
+    // LDS serves a wave's access in passes of 128 bytes over 32 banks: 32
+    // lanes of a 4-byte access, 16 of an 8-byte one (measured: a 16 x 4
+    // block of FP64 slots is conflict-free with rows 23 long, an 8 x 8 one
+    // only with rows an odd multiple of 8 modulo 16).  Smallest row >= need
+    // that is an odd multiple of w modulo the elements of one pass
+    // (per_pass), so that the w-wide rows of a pass fall on distinct banks;
+    // need itself when a pass holds one row; 0 if none within 2x need.
+    // w = tx for the rows r, r + 1, ... of a pass; a pass of 32 FP32 holds
+    // two 16-wide rows, and with the lanes' bits 4 and 5 swapped (lane_swz)
+    // these are rows r and r + 2, which w = 8 keeps apart with rows of 24
+    // where rows r and r + 1 would need 48.
+    auto pad_row = [&](int need, int per_pass, int w) {
+        if (w >= per_pass) return need;
+        if (w <= 0 || per_pass % w) return 0;
         int row = need;
-        while (!((row % per_pass) % tx == 0 && ((row % per_pass) / tx) % 2 == 1)) ++row;
+        while (!((row % per_pass) % w == 0 && ((row % per_pass) / w) % 2 == 1)) ++row;
         return row <= 2 * need ? row : 0;
     };
     // LDS bytes of the field (F) or current (J) stage for a margin per axis
@@ -739,10 +750,11 @@ pic_status pic_init(pic_ctx **out, const pic_box_desc *boxes, int32_t nboxes, pi
         }
         return field ? (mx + 15) / 16 * 16 : mx;
     };
-    const int fpass = fb == 4 ? 64 : 32;
+    const int fpass = fb == 4 ? 32 : 16;
     auto layout = [&](const int *mg, bool padf, bool padj, int &frow, int &jrow) {
-        frow = padf ? pad_row(tx + halo_gl(o) + halo_gh(o) + 2 * mg[0], fpass) : 0;
-        jrow = padj ? pad_row(tx + halo_jl(o) + halo_jh(o) + 2 * mg[0], 32) : 0;
+        frow = padf ? pad_row(tx + halo_gl(o) + halo_gh(o) + 2 * mg[0], fpass,
+                              tx == 16 && fb == 4 ? 8 : tx) : 0;
+        jrow = padj ? pad_row(tx + halo_jl(o) + halo_jh(o) + 2 * mg[0], 16, tx) : 0;
         return stage_bytes(true, mg, frow) + stage_bytes(false, mg, jrow);
     };
     {
@@ -781,6 +793,7 @@ pic_status pic_init(pic_ctx **out, const pic_box_desc *boxes, int32_t nboxes, pi
         c->lds_bytes = layout(mg, padf, padj, fr, jr);
         c->frow = fr;
         c->jrow = jr;
+        c->lane_swz = tx == 16 && fb == 4 && fr > 0;
         for (int k = 0; k < 3; ++k) c->margin[k] = mg[k];
         c->lds_field_bytes = stage_bytes(true, mg, fr);
     }

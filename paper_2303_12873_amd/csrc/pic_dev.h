@@ -81,6 +81,10 @@ struct KParams {
     int margin[3];            // cells staged around each tile per axis (0 or 1)
     int jrow;                 // minimum row length of the LDS current tile
     int frow;                 // minimum row length of the LDS field tile
+    int lane_swz;             // 1: slots of a wave swap lane bits 4 and 5, so
+                              // that with 16-wide tile rows the 32 lanes of
+                              // one LDS pass of a 4-byte field read hold
+                              // rows r and r + 2 (see frow)
     int *strag_count;         // per species: entries in its straggler list
     // species of each box (CSR: box_sp[box_sp_off[b] .. box_sp_off[b+1]))
     const int *box_sp_off;

@@ -16,8 +16,11 @@ constexpr int MB_LDS_WORDS = 8192;   // 32 KB of 4-byte words
 // consecutive lanes share a slot; 2: every lane of the wave the same slot;
 // 3: distinct slots two words apart; 4: distinct slots 15 words apart;
 // 5 / 6: the lanes of a wave on an 8 x 8 block of cells of a tile whose rows
-// are 15 / 24 slots long (the current tile's row without / with padding).
+// are 15 / 24 slots long (the current tile's row without / with padding);
+// 7 / 8: on a 16 x 4 block, rows 23 / 24 long; 9 / 10: the same with lane
+// bits 4 and 5 swapped (a half-wave on rows r and r + 2).
 __device__ inline int slot(int lane, int wave, int pattern) {
+    const int sw = lane ^ ((((lane >> 4) ^ (lane >> 5)) & 1) * 48);
     switch (pattern) {
         case 0: return wave * 64 + lane;
         case 1: return wave * 16 + lane / 4;
@@ -25,7 +28,11 @@ __device__ inline int slot(int lane, int wave, int pattern) {
         case 3: return wave * 128 + 2 * lane;
         case 4: return (wave * 64 + lane) * 15 % 4096;
         case 5: return (lane & 7) + 15 * (lane >> 3) + 3 * wave;
-        default: return (lane & 7) + 24 * (lane >> 3) + 3 * wave;
+        case 6: return (lane & 7) + 24 * (lane >> 3) + 3 * wave;
+        case 7: return (lane & 15) + 23 * (lane >> 4) + 3 * wave;
+        case 8: return (lane & 15) + 24 * (lane >> 4) + 3 * wave;
+        case 9: return (sw & 15) + 23 * (sw >> 4) + 3 * wave;
+        default: return (sw & 15) + 24 * (sw >> 4) + 3 * wave;
     }
 }
 

@@ -1036,7 +1036,11 @@ __device__ __forceinline__ void process_range(const KParams &prm, const DevBox &
                                               const LdsField<typename P::FieldT> &lf,
                                               const LdsJ<typename P::Acc> &lj) {
     const DevSpecies &sp = prm.species[s];
-    const int tid = threadIdx.x, bs = blockDim.x;
+    // lane_swz: hardware lane bits 4 and 5 trade places (a bijection on each
+    // wave's 64 slots; the block is a multiple of 64)
+    const int hw = threadIdx.x;
+    const int tid = prm.lane_swz ? hw ^ ((((hw >> 4) ^ (hw >> 5)) & 1) * 48) : hw;
+    const int bs = blockDim.x;
     const int n = p1 - p0;
     if (n <= 0) return;
     const int S = prm.lane_stride > 1 ? prm.lane_stride : 1;

@@ -15,7 +15,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 MB_PATH = os.path.join(_HERE, "libpic_mb.so")
 PATTERNS = {0: "distinct consecutive", 1: "4 lanes per slot", 2: "whole wave one slot",
             3: "distinct, 2-word stride", 4: "distinct, 15-word stride",
-            5: "8x8 cells, row 15", 6: "8x8 cells, row 24"}
+            5: "8x8 cells, row 15", 6: "8x8 cells, row 24", 7: "16x4 cells, row 23",
+            8: "16x4 cells, row 24", 9: "16x4 cells, row 23, lane bits 4/5 swapped",
+            10: "16x4 cells, row 24, lane bits 4/5 swapped"}
 
 
 def _lib():

@@ -470,6 +470,28 @@ def test_padded_lds_rows(prec, tol, pad):
 
 
 @pytest.mark.parametrize("prec,tol", ((pic.PIC_FP64, TOL64), (pic.PIC_FP32_SPLIT, TOL32)))
+@pytest.mark.parametrize("stride,order", ((4, -1), (1, 2)))
+def test_swapped_lane_rows_16_wide(prec, tol, stride, order):
+    """16-wide tiles with padded FP32 field rows (pad 2): the library swaps
+    lane bits 4 and 5 of every wave (each 32-lane LDS pass on rows r and
+    r + 2); the slot -> particle mapping stays a bijection, on the strided
+    and the quad path (FP64: padded rows without the swap)."""
+    wl = pi.uniform_box((32, 16, 12), 4, 0.05, 0.3, 3, 2400, "cpu", tile=(16, 8, 4),
+                        fields="fourier", species=("e", "i"))
+    Eo, Bo, Jo, sps = _oracle_steps(wl, 3)
+    run = GpuRun(wl, prec, kernel=pic.PIC_KERNEL_BATCHED, lane_stride=stride, cell_order=order,
+                 chunk=8192, block=1024 if prec == pic.PIC_FP32_SPLIT else 512, pad=2)
+    run.sort()
+    for _ in range(3):
+        run.particles()
+        pic.pic_fdtd_step(run.ctx, run.f)
+    run.check()
+    E, B, J = run.fields_np()
+    assert rel_l2(J, Jo) <= tol and rel_l2(E, Eo) <= tol, (rel_l2(J, Jo), rel_l2(E, Eo))
+    run.free()
+
+
+@pytest.mark.parametrize("prec,tol", ((pic.PIC_FP64, TOL64), (pic.PIC_FP32_SPLIT, TOL32)))
 @pytest.mark.parametrize("margin", (0, -1))
 def test_margin_on_some_axes(prec, tol, margin):
     """Order-3 16x8x4 tiles: the staged margin does not fit on every axis,
