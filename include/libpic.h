@@ -4,12 +4,15 @@
  * charge-conserving (Esirkepov) current deposition and the Yee FDTD update,
  * plus the per-tile particle sort that keeps the LDS-tiled kernels fed.
  *
- * The paper (Sec. II) places its code among "fully-kinetic, electromagnetic
- * particle-in-cell" models, explicit in time t, and (Sec. III.A) measures it
- * by the rate of particle and cell updates per second; the operations below
- * are the four steps of such a time step, as defined by the published
- * methods: B-spline shapes, Boris (1970), Esirkepov (Comput. Phys. Commun.
- * 135, 2001) and Yee (IEEE TAP 14, 1966).
+ * The paper (Sec. II) places its code among explicit-in-time, fully kinetic
+ * electromagnetic PIC models and (Sec. III.A) measures it by the rate of
+ * particle and cell updates per second; it prints no equation of the step.
+ * The operations below are the four parts of such a time step as the
+ * published methods define them: B-spline shape factors, the relativistic
+ * Boris rotation (Boris 1970), Esirkepov's charge-conserving current
+ * deposition (Comput. Phys. Commun. 135, 2001, 144) and Yee's staggered-grid
+ * FDTD update (IEEE TAP 14, 1966, 302).  Each entry point names the method
+ * it follows.
  *
  * Conventions (every entry point)
  *   - Normalised units: c = eps0 = mu0 = 1.  u = gamma v.
@@ -172,32 +175,52 @@ typedef struct pic_ctx pic_ctx;
 pic_status pic_init(pic_ctx **ctx, const pic_box_desc *boxes, int32_t nboxes,
                     pic_precision prec, void *stream, const pic_tuning *tuning);
 
-/* Per-tile stable counting sort (least-significant-digit radix passes over
- * the tile id): every species' particle arrays are permuted IN PLACE so that
- * particles are grouped by tile id = tx + ntx*(ty + nty*tz) of their cell,
- * ties kept in their previous order (with pic_tuning.cell_order, ordered by
- * cell inside each tile first).  The per-tile offsets are kept in the
- * context for the tiled kernels.  Optional outputs, each an array of nsp
- * device pointers (the array itself on the host; it or any entry may be
- * NULL): perm_out[s][i] = previous index of the particle now at i;
- * key_out[s][i] = its tile id; tile_offset_out[s] = ntiles+1 exclusive
- * offsets.  Species must be passed in the same order to every call. */
+/* Per-tile stable counting sort.  The paper is silent on particle ordering;
+ * this is the library's own data structure: it groups particles by the tile
+ * of their cell so the tiled kernels can stage each tile's E/B and J in LDS.
+ * Least-significant-digit radix passes over the tile id permute every
+ * species' particle arrays IN PLACE so that particles are grouped by tile
+ * id = tx + ntx*(ty + nty*tz) of their cell, ties kept in their previous
+ * order (with pic_tuning.cell_order, ordered by cell inside each tile first);
+ * particles with an invalid position go to a bucket after the last tile.
+ * The per-tile offsets are kept in the context for the tiled kernels.
+ * Optional outputs, each an array of nsp device pointers (the array itself
+ * on the host; it or any entry may be NULL; each entry owned by the caller,
+ * np ints, or ntiles+1 for offsets): perm_out[s][i] = previous index of the
+ * particle now at i; key_out[s][i] = its tile id; tile_offset_out[s] =
+ * ntiles+1 exclusive offsets.  Species must be passed in the same order to
+ * every call.  Errors: PIC_ERR_ARG (bad species table), PIC_ERR_STATE
+ * (between pic_gather_push and pic_deposit_J), PIC_ERR_OOM (scratch). */
 pic_status pic_sort_tiles(pic_ctx *ctx, const pic_species *sp, int32_t nsp,
                           int32_t *const *perm_out, int32_t *const *key_out,
                           int32_t *const *tile_offset_out);
 
-/* Gather E, B at x^n with order-n shapes (each component on its own Yee
- * points), Boris-push u^(n-1/2) -> u^(n+1/2), advance positions to x^(n+1).
+/* Field gather and particle push.  Gather: E, B at x^n as the sum over the
+ * Yee points of each component of the field value times the product of
+ * order-n B-spline shape factors along the three axes (the same order on
+ * every stagger).  Push: the relativistic Boris rotation (Boris 1970)
+ * u^(n-1/2) -> u^(n+1/2) with h = q dt / (2 m): half electric kick, magnetic
+ * rotation by t = h B / gamma-, half electric kick; then the advance
+ * x^(n+1) = x^n + dt u^(n+1/2) / (gamma^(n+1/2) dx_d) per axis.  Both are
+ * the particle half of the explicit PIC step the paper names (Sec. II).
  * x^n is kept in context scratch for pic_deposit_J.  Until that call FP64
  * positions are left unwrapped (within one cell outside [0, n)); split
- * positions are stored wrapped, their cell change kept in scratch. */
+ * positions are stored wrapped, their cell change kept in scratch.
+ * A particle with |dx| >= 0.999 cell or a non-finite value is left in place
+ * and latches PIC_ERR_RANGE for pic_check.  Tiled/batched forms need a
+ * preceding pic_sort_tiles (else PIC_ERR_STATE). */
 pic_status pic_gather_push(pic_ctx *ctx, const pic_fields *f, pic_species *sp,
                            int32_t nsp);
 
-/* Zero J of every box, deposit the Esirkepov current of the move
- * x^n -> x^(n+1) recorded by the last pic_gather_push, then wrap positions
- * periodically.  PIC_ERR_STATE without a preceding pic_gather_push on the
- * same species. */
+/* Charge-conserving current deposition of Esirkepov (Comput. Phys. Commun.
+ * 135, 2001, 144): zero J of every box, then for each particle the move
+ * x^n -> x^(n+1) recorded by the last pic_gather_push is deposited as
+ * W^x = dSx (S0y S0z + dSy S0z / 2 + S0y dSz / 2 + dSy dSz / 3) (and
+ * cyclically), J_x = -(q w dx / (dt dV)) times the running sum of W^x along
+ * x, so that the discrete continuity equation d(rho)/dt + div J = 0 holds
+ * to rounding.  Then positions are wrapped periodically.  J is FP64 in both
+ * precisions, accumulated with atomics (order of the sum unspecified).
+ * PIC_ERR_STATE without a preceding pic_gather_push on the same species. */
 pic_status pic_deposit_J(pic_ctx *ctx, pic_fields *f, pic_species *sp,
                          int32_t nsp);
 
@@ -206,8 +229,12 @@ pic_status pic_deposit_J(pic_ctx *ctx, pic_fields *f, pic_species *sp,
 pic_status pic_advance(pic_ctx *ctx, pic_fields *f, pic_species *sp,
                        int32_t nsp);
 
-/* Yee update of every box: B -= (dt/2) curl E; E += dt (curl B - J);
- * B -= (dt/2) curl E.  Periodic. */
+/* Yee's staggered-grid FDTD update (IEEE TAP 14, 1966, 302), periodic, of
+ * every box: B -= (dt/2) curl E; E += dt (curl B - J); B -= (dt/2) curl E,
+ * with the curls taken as one-cell differences on the Yee stagger (2D: no
+ * d/dy terms), so E and B are co-timed at integer steps for the next gather.
+ * The field half of the explicit EM step the paper names (Sec. II).
+ * E, B in the context's precision, J FP64; all arrays owned by the caller. */
 pic_status pic_fdtd_step(pic_ctx *ctx, pic_fields *f);
 
 /* One whole step (optional sort, pic_advance, pic_fdtd_step) recorded once
@@ -227,6 +254,22 @@ pic_status pic_deposit_rho(pic_ctx *ctx, const pic_species *sp, int32_t nsp,
 pic_status pic_div_edge(pic_ctx *ctx, int32_t box, double *const v[3],
                         double *out);
 
+/* Energies of box `box`, a check beside the step, not part of it: the
+ * electromagnetic field energy and the relativistic kinetic energy
+ * m (gamma - 1) c^2 of the particles of the fully kinetic model (Sec. II),
+ * whose sum the explicit scheme keeps up to its truncation error.  FP64
+ * sums on the device into out (a DEVICE array of 2 + nsp doubles owned by
+ * the caller, overwritten):
+ *   out[0] = 1/2 sum over cells of E.E dV,  out[1] = 1/2 sum of B.B dV
+ *            (eps0 = mu0 = 1; each component at its own Yee point);
+ *   out[2 + s] = sum over the particles of species s of w m (gamma - 1),
+ *            gamma - 1 evaluated as u.u / (1 + gamma); 0 for a species of
+ *            another box.
+ * Summation order across workgroups is unspecified (FP64 atomics).
+ * Errors: PIC_ERR_ARG (bad box, NULL out or field pointer, bad species). */
+pic_status pic_energy(pic_ctx *ctx, const pic_fields *f, const pic_species *sp,
+                      int32_t nsp, int32_t box, double *out);
+
 /* Wait for the stream and report the first device-side error (then clear). */
 pic_status pic_check(pic_ctx *ctx);
 
@@ -240,16 +283,17 @@ const char *pic_last_error(void);
 /* Number of workgroups the context's kernels fill the device with (CUs). */
 int32_t pic_device_cus(pic_ctx *ctx);
 
-/* Timing of the tiled particle kernel (TILED/BATCHED forms).  With on != 0
- * every later launch of it -- by pic_advance, pic_gather_push,
- * pic_deposit_J, or inside the graph of pic_step (graphs are recorded
- * separately with and without timing) -- is bracketed by two one-thread
- * kernels on the context's stream that store the device's constant-rate
- * wall clock (HIP events recorded inside a graph give no elapsed time on
- * this runtime).  pic_kernel_ms waits for the stream and returns in *ms the
- * time between the two stamps of the most recent timed launch (the kernel
- * plus two launch gaps of a few microseconds); PIC_ERR_STATE if none was
- * recorded since pic_set_timing. */
+/* Timing of the tiled particle kernels (TILED/BATCHED forms).  With on != 0
+ * every later launch of the tiled kernel and the straggler kernel that
+ * follows it -- by pic_advance, pic_gather_push, pic_deposit_J, or inside
+ * the graph of pic_step (graphs are recorded separately with and without
+ * timing) -- is bracketed by two one-thread kernels on the context's stream
+ * that store the device's constant-rate wall clock (HIP events recorded
+ * inside a graph give no elapsed time on this runtime).  pic_kernel_ms
+ * waits for the stream and returns in *ms the time between the two stamps
+ * of the most recent timed launch (both kernels plus the launch gaps, a few
+ * microseconds each); PIC_ERR_STATE if none was recorded since
+ * pic_set_timing. */
 pic_status pic_set_timing(pic_ctx *ctx, int32_t on);
 pic_status pic_kernel_ms(pic_ctx *ctx, float *ms);
 

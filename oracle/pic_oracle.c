@@ -388,6 +388,9 @@ void orc_div_j(const orc_grid *g, double *const J[3], double *divj)
             }
 }
 
+/* Electromagnetic field energy 1/2 sum over cells of (E.E + B.B) dV in
+ * these units (eps0 = mu0 = 1), every component sampled at its own Yee
+ * point of the cell. */
 double orc_field_energy(const orc_grid *g, double *const E[3],
                         double *const B[3])
 {
@@ -400,13 +403,16 @@ double orc_field_energy(const orc_grid *g, double *const E[3],
     return 0.5 * s * dV;
 }
 
+/* Relativistic kinetic energy m (gamma - 1) c^2 per physical particle,
+ * times the weight.  gamma - 1 is evaluated as u.u / (1 + gamma), the same
+ * quantity without the cancellation of sqrt(1 + u.u) - 1 at |u| << 1. */
 double orc_kinetic_energy(const orc_species *S)
 {
     double s = 0.0;
     for (int64_t p = 0; p < S->np; ++p) {
         double u2 = S->u[0][p] * S->u[0][p] + S->u[1][p] * S->u[1][p] +
                     S->u[2][p] * S->u[2][p];
-        s += S->w[p] * S->m * (sqrt(1.0 + u2) - 1.0);
+        s += S->w[p] * S->m * (u2 / (1.0 + sqrt(1.0 + u2)));
     }
     return s;
 }

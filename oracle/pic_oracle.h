@@ -6,9 +6,9 @@
  * baseline leg of the benchmark load it.  It shares no code, header, table
  * or helper with the GPU library.
  *
- * What it follows.  The paper (Sec. II, "fully-kinetic, electromagnetic
- * particle-in-cell", explicit in time t; Sec. IV, time-based EM code) names
- * the method but prints no equation of it, so each function below is the
+ * What it follows.  The paper (Sec. II: an explicit, fully kinetic
+ * electromagnetic PIC model; Sec. IV: the time-based EM code) names the
+ * method but prints no equation of it, so each function below is the
  * textbook definition of the published method the step is built from:
  *   - B-spline particle shape factors of order 1..3;
  *   - the relativistic Boris rotation (Boris 1970);

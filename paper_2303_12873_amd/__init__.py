@@ -26,7 +26,7 @@ PIC_FP64, PIC_FP32_SPLIT = 0, 1
 PIC_KERNEL_DIRECT, PIC_KERNEL_TILED, PIC_KERNEL_BATCHED = 0, 1, 2
 
 EXPORTED = ["pic_init", "pic_sort_tiles", "pic_gather_push", "pic_deposit_J", "pic_advance",
-            "pic_fdtd_step", "pic_step", "pic_deposit_rho", "pic_div_edge", "pic_check",
+            "pic_fdtd_step", "pic_step", "pic_deposit_rho", "pic_div_edge", "pic_energy", "pic_check",
             "pic_free", "pic_status_str", "pic_last_error", "pic_device_cus", "pic_set_timing",
             "pic_kernel_ms"]
 
@@ -78,6 +78,7 @@ def lib():
         L.pic_step.argtypes = [P, C.POINTER(pic_fields), C.POINTER(pic_species), I, I]
         L.pic_deposit_rho.argtypes = [P, C.POINTER(pic_species), I, I, P]
         L.pic_div_edge.argtypes = [P, I, P, P]
+        L.pic_energy.argtypes = [P, C.POINTER(pic_fields), C.POINTER(pic_species), I, I, P]
         L.pic_check.argtypes = [P]
         L.pic_free.argtypes = [P]
         L.pic_status_str.argtypes = [I]
@@ -289,6 +290,18 @@ def pic_deposit_rho(ctx, species, box: int, rho: torch.Tensor):
 def pic_div_edge(ctx, box: int, v: Sequence[torch.Tensor], out: torch.Tensor):
     arr = (C.c_void_p * 3)(*[_ptr(t) for t in v])
     _check(lib().pic_div_edge(ctx, box, C.cast(arr, C.c_void_p), _ptr(out)))
+
+
+def pic_energy(ctx, fields: DeviceFields, species, box: int = 0, out: torch.Tensor = None):
+    """FP64 energies of one box on the device: returns ``out`` (2 + nsp
+    doubles): 1/2 sum E.E dV, 1/2 sum B.B dV, then sum w m (gamma - 1) per
+    species (0 for species of other boxes)."""
+    if out is None:
+        out = torch.empty(2 + len(species), dtype=torch.float64, device=fields.E.device)
+    f = fields.c()
+    _check(lib().pic_energy(ctx, C.byref(f), _species_array(species), len(species), box,
+                            _ptr(out)))
+    return out
 
 
 def pic_check(ctx):

@@ -30,12 +30,16 @@ COMMON = [
     f"-I{os.path.join(ROOT, 'include')}",
 ]
 
+# pic_particles.hip once per (shape order, precision, part): part 0 the
+# direct / straggler / split-call kernels, 1 the fused tiled kernels, 2 the
+# fused persistent kernels; compiled in parallel.
 UNITS = [
     ("libpic.hip", "libpic.o", []),
     ("pic_aux.hip", "pic_aux.o", []),
-    ("pic_particles.hip", "pic_particles_o1.o", ["-DPIC_ORDER=1"]),
-    ("pic_particles.hip", "pic_particles_o2.o", ["-DPIC_ORDER=2"]),
-    ("pic_particles.hip", "pic_particles_o3.o", ["-DPIC_ORDER=3"]),
+] + [
+    ("pic_particles.hip", f"pic_particles_o{o}_p{p}_t{t}.o",
+     [f"-DPIC_ORDER={o}", f"-DPIC_PREC={p}", f"-DPIC_PART={t}"])
+    for o in (3, 2, 1) for p in (1, 0) for t in (2, 1, 0)
 ]
 
 
@@ -67,7 +71,7 @@ def build_microbench(extra_flags=()) -> str:
 
 def build(verbose: bool = False, extra_flags=()) -> str:
     os.makedirs(BUILD_DIR, exist_ok=True)
-    jobs = min(len(UNITS), max(1, (os.cpu_count() or 2)))
+    jobs = min(len(UNITS), max(1, min(16, os.cpu_count() or 2)))
     with cf.ThreadPoolExecutor(jobs) as ex:
         objs = list(ex.map(lambda u: _compile(u, extra_flags), UNITS))
     tmp = OUT + ".tmp"

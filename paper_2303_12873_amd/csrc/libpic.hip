@@ -149,6 +149,15 @@ int key_bits(int nkeys) {
     return b < 1 ? 1 : b;
 }
 
+// Captured step graphs hold the addresses of the context's scratch buffers.
+// Every site that frees or reallocates one of them (after waiting for the
+// stream) drops the cached graphs, so none is ever replayed on freed memory;
+// the next pic_step records afresh.
+void drop_graphs(pic_ctx *c) {
+    for (auto &kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+    c->graphs.clear();
+}
+
 pic_status check_box(const pic_box_desc &b, int i) {
     std::string w = "box " + std::to_string(i) + ": ";
     if (b.dim != 2 && b.dim != 3) return fail(PIC_ERR_ARG, w + "dim must be 2 or 3");
@@ -178,6 +187,7 @@ pic_status check_box(const pic_box_desc &b, int i) {
 pic_status ensure_slot_scratch(pic_ctx *c, Slot &sl, long long np) {
     const int pb = c->prec == PIC_FP64 ? 8 : 4;
     if (sl.cap >= np && sl.prec_bytes == pb) return PIC_OK;
+    drop_graphs(c);
     for (int d = 0; d < 3; ++d) { dfree(sl.xo[d]); dfree(sl.offo[d]); }
     dfree(sl.cello);
     dfree(sl.carry);
@@ -231,7 +241,6 @@ pic_status bind_species(pic_ctx *c, const pic_species *sp, int nsp, bool need_pu
     if ((int)c->slots.size() < nsp) c->slots.resize(nsp);
     std::vector<DevSpecies> t(nsp);
     std::vector<int> prefix(nsp + 1, 0);
-    bool realloc_happened = false;
     for (int s = 0; s < nsp; ++s) {
         const pic_species &p = sp[s];
         Slot &sl = c->slots[s];
@@ -248,20 +257,20 @@ pic_status bind_species(pic_ctx *c, const pic_species *sp, int nsp, bool need_pu
             if (c->capturing) return fail(PIC_ERR_STATE, "scratch growth during graph capture");
             (void)hipStreamSynchronize(c->stream);
             if ((st = ensure_slot_scratch(c, sl, p.np)) != PIC_OK) return st;
-            realloc_happened = true;
         }
         if (sl.tile_cap < b.ntiles + 2) {
             if (c->capturing) return fail(PIC_ERR_STATE, "scratch growth during graph capture");
             (void)hipStreamSynchronize(c->stream);
+            drop_graphs(c);
             dfree(sl.tile_off);
             if ((st = dalloc(&sl.tile_off, (size_t)b.ntiles + 2)) != PIC_OK) return st;
             sl.tile_cap = b.ntiles + 2;
             sl.sorted = false;
-            realloc_happened = true;
         }
         if (c->tun.kernel != PIC_KERNEL_DIRECT && sl.strag_cap < p.np) {
             if (c->capturing) return fail(PIC_ERR_STATE, "scratch growth during graph capture");
             (void)hipStreamSynchronize(c->stream);
+            drop_graphs(c);
             dfree(sl.strag);
             if ((st = dalloc(&sl.strag, (size_t)p.np)) != PIC_OK) return st;
             sl.strag_cap = p.np;
@@ -290,13 +299,13 @@ pic_status bind_species(pic_ctx *c, const pic_species *sp, int nsp, bool need_pu
                    (c->tun.quad_spread == 0 && p.np >= 6 * c->hbox[p.box].ncells);
         prefix[s + 1] = prefix[s] + b.ntiles;
     }
-    (void)realloc_happened;
     bool same = (int)c->hsp.size() == nsp &&
                 (nsp == 0 || std::memcmp(c->hsp.data(), t.data(), nsp * sizeof(DevSpecies)) == 0);
     if (!same) {
         if (c->capturing) return fail(PIC_ERR_STATE, "species binding changed during graph capture");
         (void)hipStreamSynchronize(c->stream);
         if (c->dsp_cap < nsp + 1) {
+            drop_graphs(c);
             dfree(c->dsp);
             dfree(c->dprefix);
             dfree(c->strag_count);
@@ -367,16 +376,27 @@ KParams make_params(pic_ctx *c, const pic_fields *f, int nsp) {
     return k;
 }
 
+#define PIC_UNITS(F, N) {{F##_o##N##_p0_t0, F##_o##N##_p0_t1, F##_o##N##_p0_t2}, \
+                        {F##_o##N##_p1_t0, F##_o##N##_p1_t1, F##_o##N##_p1_t2}}
+// [order - 1][precision][part] (parts as in pic_aux.h)
+const ParticleLauncher k_launch[3][2][3] = {PIC_UNITS(launch_particles, 1),
+                                            PIC_UNITS(launch_particles, 2),
+                                            PIC_UNITS(launch_particles, 3)};
+const LdsLimiter k_lds_limit[3][2][3] = {PIC_UNITS(particles_lds_limit, 1),
+                                         PIC_UNITS(particles_lds_limit, 2),
+                                         PIC_UNITS(particles_lds_limit, 3)};
+#undef PIC_UNITS
+const RhoLauncher k_rho_launch[3][2] = {{launch_rho_o1_p0_t0, launch_rho_o1_p1_t0},
+                                        {launch_rho_o2_p0_t0, launch_rho_o2_p1_t0},
+                                        {launch_rho_o3_p0_t0, launch_rho_o3_p1_t0}};
+
 // form: 0 direct, 1 tiled, 2 batched (persistent), 3 stragglers of 1/2.
 hipError_t launch_particles(pic_ctx *c, const KParams &k, int form, int mode, int grid,
                             int species) {
     const int prec = c->prec == PIC_FP64 ? 0 : 1;
-    const int block = c->tun.block;
-    switch (c->order) {
-        case 1: return launch_particles_o1(k, prec, form, mode, c->dims, grid, block, c->lds_bytes, species, c->stream);
-        case 2: return launch_particles_o2(k, prec, form, mode, c->dims, grid, block, c->lds_bytes, species, c->stream);
-        default: return launch_particles_o3(k, prec, form, mode, c->dims, grid, block, c->lds_bytes, species, c->stream);
-    }
+    const int part = (mode == MODE_FUSED && (form == 1 || form == 2)) ? form : 0;
+    return k_launch[c->order - 1][prec][part](k, form, mode, c->dims, grid, c->tun.block,
+                                             c->lds_bytes, species, c->stream);
 }
 
 pic_status check_fields(pic_ctx *c, const pic_fields *f, bool need_eb) {
@@ -422,12 +442,12 @@ pic_status run_particles(pic_ctx *c, pic_fields *f, pic_species *sp, int nsp, in
             int grid = c->cus * c->tun.wg_per_cu;
             HIP_TRY(launch_particles(c, k, 2, mode, grid, 0));
         }
+        // particles that had left their tile plus margin since the sort
+        HIP_TRY(launch_particles(c, k, 3, mode, c->cus * 2, 0));
         if (c->timing) {
             HIP_TRY(launch_stamp(c->stamps + 1, c->stream));
             c->timed = true;
         }
-        // particles that had left their tile plus margin since the sort
-        HIP_TRY(launch_particles(c, k, 3, mode, c->cus * 2, 0));
     }
     for (int s = 0; s < nsp; ++s) {
         if (mode == MODE_PUSH) c->slots[s].pushed = true;
@@ -441,6 +461,7 @@ pic_status ensure_sort_scratch(pic_ctx *c, long long np, long long nitems_cap) {
     if (c->sort_cap < np) {
         if (c->capturing) return fail(PIC_ERR_STATE, "scratch growth during graph capture");
         (void)hipStreamSynchronize(c->stream);
+        drop_graphs(c);
         for (int i = 0; i < 2; ++i) { dfree(c->keys[i]); dfree(c->vals[i]); }
         if (c->tmp) { (void)hipFree(c->tmp); c->tmp = nullptr; }
         for (int i = 0; i < 2; ++i) {
@@ -460,6 +481,7 @@ pic_status ensure_sort_scratch(pic_ctx *c, long long np, long long nitems_cap) {
     if (c->counts_cap < need_counts) {
         if (c->capturing) return fail(PIC_ERR_STATE, "scratch growth during graph capture");
         (void)hipStreamSynchronize(c->stream);
+        drop_graphs(c);
         dfree(c->counts);
         if ((st = dalloc(&c->counts, need_counts)) != PIC_OK) return st;
         c->counts_cap = need_counts;
@@ -467,6 +489,7 @@ pic_status ensure_sort_scratch(pic_ctx *c, long long np, long long nitems_cap) {
     if (c->scan_cap < need_scan) {
         if (c->capturing) return fail(PIC_ERR_STATE, "scratch growth during graph capture");
         (void)hipStreamSynchronize(c->stream);
+        drop_graphs(c);
         dfree(c->scan_scr);
         if ((st = dalloc(&c->scan_scr, need_scan)) != PIC_OK) return st;
         c->scan_cap = need_scan;
@@ -475,6 +498,7 @@ pic_status ensure_sort_scratch(pic_ctx *c, long long np, long long nitems_cap) {
         if (c->item_slot_cap < c->nbslots + 1) {
             if (c->capturing) return fail(PIC_ERR_STATE, "scratch growth during graph capture");
             (void)hipStreamSynchronize(c->stream);
+            drop_graphs(c);
             dfree(c->item_counts);
             dfree(c->item_starts);
             int cap = c->nbslots + 64;
@@ -485,6 +509,7 @@ pic_status ensure_sort_scratch(pic_ctx *c, long long np, long long nitems_cap) {
         if (c->items_cap < nitems_cap) {
             if (c->capturing) return fail(PIC_ERR_STATE, "scratch growth during graph capture");
             (void)hipStreamSynchronize(c->stream);
+            drop_graphs(c);
             dfree(c->items);
             if ((st = dalloc(&c->items, (size_t)nitems_cap)) != PIC_OK) return st;
             c->items_cap = nitems_cap;
@@ -834,9 +859,12 @@ pic_status pic_init(pic_ctx **out, const pic_box_desc *boxes, int32_t nboxes, pi
     }
     if (t.kernel != PIC_KERNEL_DIRECT) {
         const int precb = prec == PIC_FP64 ? 0 : 1;
-        hipError_t e = o == 1 ? particles_lds_limit_o1(precb, (int)c->lds_bytes)
-                              : (o == 2 ? particles_lds_limit_o2(precb, (int)c->lds_bytes)
-                                        : particles_lds_limit_o3(precb, (int)c->lds_bytes));
+        // The limit is per kernel and shared by every context of the process:
+        // set it to the largest stage any context may use, so a later context
+        // with a smaller stage cannot lower it below an earlier one's need.
+        hipError_t e = hipSuccess;
+        for (int part = 0; part < 3 && e == hipSuccess; ++part)
+            e = k_lds_limit[o - 1][precb][part](LDS_BYTES_MAX);
         if (e != hipSuccess) {
             pic_free(c);
             return fail(PIC_ERR_DEVICE, std::string("LDS limit: ") + hipGetErrorString(e));
@@ -936,9 +964,7 @@ pic_status pic_deposit_rho(pic_ctx *c, const pic_species *sp, int32_t nsp, int32
     const int prec = c->prec == PIC_FP64 ? 0 : 1;
     for (int s = 0; s < nsp; ++s) {
         if (sp[s].box != box || sp[s].np == 0) continue;
-        hipError_t e = c->order == 1 ? launch_rho_o1(k, prec, s, sp[s].np, rho, c->stream)
-                                     : (c->order == 2 ? launch_rho_o2(k, prec, s, sp[s].np, rho, c->stream)
-                                                      : launch_rho_o3(k, prec, s, sp[s].np, rho, c->stream));
+        hipError_t e = k_rho_launch[c->order - 1][prec](k, s, sp[s].np, rho, c->stream);
         HIP_TRY(e);
     }
     return PIC_OK;
@@ -949,6 +975,21 @@ pic_status pic_div_edge(pic_ctx *c, int32_t box, double *const v[3], double *out
     if (box < 0 || box >= c->nboxes || !v || !out || !v[0] || !v[1] || !v[2])
         return fail(PIC_ERR_ARG, "bad box or pointers");
     HIP_TRY(launch_div_edge(c->dbox, box, c->hbox[box].ncells, v, out, c->stream));
+    return PIC_OK;
+}
+
+pic_status pic_energy(pic_ctx *c, const pic_fields *f, const pic_species *sp, int32_t nsp,
+                      int32_t box, double *out) {
+    if (!c) return fail(PIC_ERR_ARG, "ctx is NULL");
+    if (box < 0 || box >= c->nboxes || !out) return fail(PIC_ERR_ARG, "bad box or out");
+    pic_status st = check_fields(c, f, true);
+    if (st != PIC_OK) return st;
+    if ((st = bind_species(c, sp, nsp, false)) != PIC_OK) return st;
+    std::vector<long long> np(std::max(nsp, 1), 0);
+    for (int s = 0; s < nsp; ++s) np[s] = sp[s].box == box ? sp[s].np : 0;
+    KParams k = make_params(c, f, nsp);
+    HIP_TRY(launch_energy(c->prec == PIC_FP64 ? 0 : 1, k.f, c->dbox, box, c->hbox[box].ncells,
+                          c->dsp, np.data(), nsp, out, c->cus, c->stream));
     return PIC_OK;
 }
 
@@ -968,7 +1009,7 @@ pic_status pic_check(pic_ctx *c) {
 pic_status pic_free(pic_ctx *c) {
     if (!c) return PIC_OK;
     (void)hipStreamSynchronize(c->stream);
-    for (auto &kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+    drop_graphs(c);
     dfree(c->stamps);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     for (auto &sl : c->slots) {

@@ -44,20 +44,42 @@ hipError_t launch_zero_j(const DevFields &f, const DevBox *boxes, const long lon
                          long long total, hipStream_t st);
 hipError_t launch_fdtd(int prec, const DevFields &f, const DevBox *boxes, const long long *fp,
                        int nb, long long total, hipStream_t st);
+// Energies (FP64, a check): out[0] = 1/2 sum E.E dV, out[1] = 1/2 sum B.B dV
+// over the cells of box bi, out[2 + s] = sum w m (gamma - 1) of species s
+// with np[s] > 0 (np: host array), else 0.  out is zeroed first.
+hipError_t launch_energy(int prec, const DevFields &f, const DevBox *boxes, int bi,
+                         long long ncells, const DevSpecies *spt, const long long *np, int nsp,
+                         double *out, int cus, hipStream_t st);
 hipError_t launch_div_edge(const DevBox *boxes, int bi, long long ncells, double *const v[3],
                            double *out, hipStream_t st);
 
-// per-order particle kernels (pic_particles.hip built with PIC_ORDER = 1, 2, 3)
+// Particle kernels: pic_particles.hip is compiled once per (shape order N,
+// precision P: 0 FP64, 1 split, part T): T = 0 holds the direct and
+// straggler kernels, the push-only / deposit-only tiled kernels and the
+// charge-density check; T = 1 the fused tiled kernels (one workgroup per
+// tile); T = 2 the fused persistent (batched) kernels.
+#define PIC_DECL_UNIT(N, P, T)                                                                   \
+    hipError_t launch_particles_o##N##_p##P##_t##T(const KParams &prm, int form, int mode,       \
+                                                   int dims, int grid, int block, size_t lds,    \
+                                                   int species, hipStream_t st);                 \
+    hipError_t particles_lds_limit_o##N##_p##P##_t##T(int bytes);
+#define PIC_DECL_RHO(N, P)                                                                       \
+    hipError_t launch_rho_o##N##_p##P##_t0(const KParams &prm, int species, long long np,       \
+                                           double *rho, hipStream_t st);
 #define PIC_DECL_ORDER(N)                                                                        \
-    hipError_t launch_particles_o##N(const KParams &prm, int prec, int form, int mode, int dims, \
-                                     int grid, int block, size_t lds, int species,               \
-                                     hipStream_t st);                                            \
-    hipError_t particles_lds_limit_o##N(int prec, int bytes);                                    \
-    hipError_t launch_rho_o##N(const KParams &prm, int prec, int species, long long np,          \
-                               double *rho, hipStream_t st);
+    PIC_DECL_UNIT(N, 0, 0) PIC_DECL_UNIT(N, 0, 1) PIC_DECL_UNIT(N, 0, 2)                         \
+    PIC_DECL_UNIT(N, 1, 0) PIC_DECL_UNIT(N, 1, 1) PIC_DECL_UNIT(N, 1, 2)                         \
+    PIC_DECL_RHO(N, 0) PIC_DECL_RHO(N, 1)
 PIC_DECL_ORDER(1)
 PIC_DECL_ORDER(2)
 PIC_DECL_ORDER(3)
 #undef PIC_DECL_ORDER
+#undef PIC_DECL_RHO
+#undef PIC_DECL_UNIT
+
+using ParticleLauncher = hipError_t (*)(const KParams &, int, int, int, int, int, size_t, int,
+                                        hipStream_t);
+using LdsLimiter = hipError_t (*)(int);
+using RhoLauncher = hipError_t (*)(const KParams &, int, long long, double *, hipStream_t);
 
 }  // namespace pic

@@ -4,6 +4,8 @@
 // arrays, work-item list of the batched kernel, J zeroing, the Yee FDTD
 // update over all boxes, and the node divergence used by the continuity
 // check.
+#include <algorithm>
+
 #include "pic_dev.h"
 #include "pic_math.h"
 #include "pic_aux.h"
@@ -445,6 +447,74 @@ __global__ void k_div_edge(const DevBox *boxes, int bi, const double *vx, const 
     out[q.c - base] = d;
 }
 
+// ------------------------------------------------------------ energies
+
+// Sum of v over a 256-thread block (4 waves: DPP-free shuffle reduction in
+// each wave, then the four wave sums through LDS); the result is valid in
+// thread 0.
+__device__ inline double block_sum256(double v, double *lds4) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    if (lane_id() == 0) lds4[wave_id()] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0) t = (lds4[0] + lds4[1]) + (lds4[2] + lds4[3]);
+    __syncthreads();
+    return t;
+}
+
+// Field energy of box bi: out[0] += 1/2 sum E.E dV, out[1] += 1/2 sum B.B dV
+// (FP64 sums; E, B in the context's precision).
+template <typename T>
+__global__ void __launch_bounds__(256) k_field_energy(DevFields f, const DevBox *boxes, int bi,
+                                                       double *out) {
+    __shared__ double red[4];
+    const DevBox &b = boxes[bi];
+    double se = 0.0, sb = 0.0;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < b.ncells; c += stride) {
+        const long long g = b.cell_base + c;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const double e = (double)((const T *)f.E[k])[g];
+            const double bb = (double)((const T *)f.B[k])[g];
+            se += e * e;
+            sb += bb * bb;
+        }
+    }
+    const double hdv = 0.5 * b.dx[0] * b.dx[1] * b.dx[2];
+    se = block_sum256(se, red);
+    sb = block_sum256(sb, red);
+    if (threadIdx.x == 0) {
+        atomicAdd(&out[0], se * hdv);
+        atomicAdd(&out[1], sb * hdv);
+    }
+}
+
+// Kinetic energy of one species: *out += sum w m (gamma - 1), with
+// gamma - 1 = u.u / (1 + gamma) (no cancellation at small |u|).
+template <typename T>
+__global__ void __launch_bounds__(256) k_kinetic_energy(const DevSpecies *spt, int s, double *out) {
+    __shared__ double red[4];
+    const DevSpecies &sp = spt[s];
+    const T *u0 = (const T *)sp.u[0], *u1 = (const T *)sp.u[1], *u2 = (const T *)sp.u[2];
+    const T *w = (const T *)sp.w;
+    double acc = 0.0;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < sp.np; i += stride) {
+        const double a = u0[i], bq = u1[i], c = u2[i];
+        const double uu = a * a + bq * bq + c * c;
+        acc += (double)w[i] * (uu / (1.0 + sqrt(1.0 + uu)));
+    }
+    acc = block_sum256(acc, red);
+    if (threadIdx.x == 0) atomicAdd(out, acc * sp.m);
+}
+
+__global__ void k_zero_doubles(double *p, int n) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.0;
+}
+
 inline unsigned blocks_for(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
 }  // namespace
@@ -630,6 +700,26 @@ hipError_t launch_fdtd(int prec, const DevFields &f, const DevBox *boxes, const 
         hipLaunchKernelGGL(k_faraday<float>, g, b, 0, st, f, boxes, fp, nb, total, 0.5);
         hipLaunchKernelGGL(k_ampere<float>, g, b, 0, st, f, boxes, fp, nb, total);
         hipLaunchKernelGGL(k_faraday<float>, g, b, 0, st, f, boxes, fp, nb, total, 0.5);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_energy(int prec, const DevFields &f, const DevBox *boxes, int bi,
+                         long long ncells, const DevSpecies *spt, const long long *np, int nsp,
+                         double *out, int cus, hipStream_t st) {
+    hipLaunchKernelGGL(k_zero_doubles, dim3(blocks_for(2 + nsp, 256)), dim3(256), 0, st, out,
+                       2 + nsp);
+    const unsigned cap = (unsigned)(cus > 0 ? 4 * cus : 1024);
+    if (ncells > 0) {
+        const unsigned g = std::min(blocks_for(ncells, 256), cap);
+        if (prec == 0) hipLaunchKernelGGL(k_field_energy<double>, dim3(g), dim3(256), 0, st, f, boxes, bi, out);
+        else hipLaunchKernelGGL(k_field_energy<float>, dim3(g), dim3(256), 0, st, f, boxes, bi, out);
+    }
+    for (int s = 0; s < nsp; ++s) {
+        if (np[s] <= 0) continue;
+        const unsigned g = std::min(blocks_for(np[s], 256), cap);
+        if (prec == 0) hipLaunchKernelGGL(k_kinetic_energy<double>, dim3(g), dim3(256), 0, st, spt, s, out + 2 + s);
+        else hipLaunchKernelGGL(k_kinetic_energy<float>, dim3(g), dim3(256), 0, st, spt, s, out + 2 + s);
     }
     return hipGetLastError();
 }

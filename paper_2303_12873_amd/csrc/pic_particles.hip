@@ -11,9 +11,10 @@
 //   batched  the tiled body driven by a persistent grid that pops
 //            (species, tile, particle chunk) items from a global queue, so
 //            tiles of very uneven population and many boxes share a launch.
-// A particle whose cell has left its tile since the last sort takes the
-// global-memory path inside the tiled forms, so results never depend on how
-// stale the sort is.
+// A particle whose cell has left its tile plus the staged margin since the
+// last sort is appended to a straggler list by the tiled forms and updated
+// through global memory by k_strag right after, so results never depend on
+// how stale the sort is.
 //
 // Precision policies: F64 (FP64 positions, momenta, fields, LDS J) and
 // Split (int32 cell + FP32 in-cell offset, FP32 momenta, fields, gather,
@@ -24,8 +25,8 @@
 #include "pic_math.h"
 #include "pic_aux.h"
 
-#ifndef PIC_ORDER
-#error "PIC_ORDER must be defined (1, 2 or 3)"
+#if !defined(PIC_ORDER) || !defined(PIC_PREC) || !defined(PIC_PART)
+#error "PIC_ORDER (1..3), PIC_PREC (0 FP64, 1 split) and PIC_PART (0..2) must be defined"
 #endif
 
 namespace pic {
@@ -69,9 +70,10 @@ __device__ inline int div_exact(int a, int d, double inv_d) {
     return q;
 }
 
-// The LDS current tile is FP64 in both forms: measured on gfx950, LDS FP32
-// atomic adds (ds_add_f32) ran ~6x slower than FP64 ones (ds_add_f64) on the
-// deposit's access pattern, and FP64 keeps the tile sum exact to 1e-16.
+// The LDS current tile is FP64 in both forms: measured on gfx950, an LDS
+// FP32 atomic add wave instruction (ds_add_f32) took ~22x the time of an
+// FP64 one (ds_add_f64) on distinct addresses, and FP64 keeps the tile sum
+// exact to 1e-16.
 struct Split {
     using R = float;
     using FieldT = float;
@@ -1275,8 +1277,8 @@ hipError_t launch_tiled_dims(const KParams &prm, int dims, int grid, int block, 
 }
 
 template <class P, int MODE>
-hipError_t launch_mode(const KParams &prm, int form, int dims, int grid, int block, size_t lds,
-                       int species, hipStream_t st) {
+hipError_t launch_mode_other(const KParams &prm, int form, int grid, int block, size_t lds,
+                             int species, hipStream_t st) {
     if (form == 0) {
         hipLaunchKernelGGL((k_direct<P, MODE>), dim3(grid), dim3(256), 0, st, prm, species);
         return hipGetLastError();
@@ -1285,40 +1287,18 @@ hipError_t launch_mode(const KParams &prm, int form, int dims, int grid, int blo
         hipLaunchKernelGGL((k_strag<P, MODE>), dim3(grid), dim3(256), 0, st, prm);
         return hipGetLastError();
     }
-    if (form == 1) return launch_tiled_dims<P, MODE, false>(prm, dims, grid, block, lds, st);
-    return launch_tiled_dims<P, MODE, true>(prm, dims, grid, block, lds, st);
-}
-
-template <class P>
-hipError_t launch_prec(const KParams &prm, int form, int mode, int dims, int grid, int block,
-                       size_t lds, int species, hipStream_t st) {
-    if (mode == MODE_PUSH) return launch_mode<P, MODE_PUSH>(prm, form, dims, grid, block, lds, species, st);
-    if (mode == MODE_DEPOSIT) return launch_mode<P, MODE_DEPOSIT>(prm, form, dims, grid, block, lds, species, st);
-    return launch_mode<P, MODE_FUSED>(prm, form, dims, grid, block, lds, species, st);
+    if constexpr (MODE == MODE_FUSED) {
+        return hipErrorInvalidValue;     // fused tiled kernels live in their own unit
+    } else {
+        if (form == 1) return launch_tiled_dims<P, MODE, false>(prm, 0, grid, block, lds, st);
+        return launch_tiled_dims<P, MODE, true>(prm, 0, grid, block, lds, st);
+    }
 }
 
 template <class P, int MODE, bool PERS, int DIMS, bool QUAD>
 hipError_t set_lds(int bytes) {
     return hipFuncSetAttribute((const void *)&k_tiled<P, MODE, PERS, DIMS, QUAD>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-}
-
-template <class P>
-hipError_t lds_limit_prec(int bytes) {
-    hipError_t e = hipSuccess;
-#define PIC_SET(M, D, Q)                                            \
-    if (e == hipSuccess) e = set_lds<P, M, false, D, Q>(bytes);     \
-    if (e == hipSuccess) e = set_lds<P, M, true, D, Q>(bytes);
-    PIC_SET(MODE_PUSH, 0, false)
-    PIC_SET(MODE_DEPOSIT, 0, false)
-    PIC_SET(MODE_FUSED, 0, false)
-    PIC_SET(MODE_FUSED, 2, false)
-    PIC_SET(MODE_FUSED, 3, false)
-    PIC_SET(MODE_FUSED, 0, true)
-    PIC_SET(MODE_FUSED, 2, true)
-    PIC_SET(MODE_FUSED, 3, true)
-#undef PIC_SET
-    return e;
 }
 
 // Charge density on nodes (FP64, a check): rho += q w S S S / dV.
@@ -1368,28 +1348,59 @@ __global__ void k_rho(KParams prm, int s, double *rho) {
 
 #define PIC_CAT2(a, b) a##b
 #define PIC_CAT(a, b) PIC_CAT2(a, b)
+#define PIC_NAME(f) PIC_CAT(PIC_CAT(PIC_CAT(f##_o, PIC_ORDER), PIC_CAT(_p, PIC_PREC)), PIC_CAT(_t, PIC_PART))
 
-hipError_t PIC_CAT(launch_particles_o, PIC_ORDER)(const KParams &prm, int prec, int form, int mode,
-                                                 int dims, int grid, int block, size_t lds,
-                                                 int species, hipStream_t st) {
-    if (prec == 0) return launch_prec<F64>(prm, form, mode, dims, grid, block, lds, species, st);
-    return launch_prec<Split>(prm, form, mode, dims, grid, block, lds, species, st);
+using PP = typename std::conditional<PIC_PREC == 0, F64, Split>::type;
+
+#if PIC_PART == 0
+// direct and straggler kernels (every mode), push-only / deposit-only tiled
+// kernels, and the charge-density check
+hipError_t PIC_NAME(launch_particles)(const KParams &prm, int form, int mode, int dims, int grid,
+                                      int block, size_t lds, int species, hipStream_t st) {
+    (void)dims;
+    if (mode == MODE_PUSH) return launch_mode_other<PP, MODE_PUSH>(prm, form, grid, block, lds, species, st);
+    if (mode == MODE_DEPOSIT) return launch_mode_other<PP, MODE_DEPOSIT>(prm, form, grid, block, lds, species, st);
+    return launch_mode_other<PP, MODE_FUSED>(prm, form, grid, block, lds, species, st);
 }
 
-hipError_t PIC_CAT(particles_lds_limit_o, PIC_ORDER)(int prec, int bytes) {
-    if (prec == 0) return lds_limit_prec<F64>(bytes);
-    return lds_limit_prec<Split>(bytes);
+hipError_t PIC_NAME(particles_lds_limit)(int bytes) {
+    hipError_t e = hipSuccess;
+    if (e == hipSuccess) e = set_lds<PP, MODE_PUSH, false, 0, false>(bytes);
+    if (e == hipSuccess) e = set_lds<PP, MODE_PUSH, true, 0, false>(bytes);
+    if (e == hipSuccess) e = set_lds<PP, MODE_DEPOSIT, false, 0, false>(bytes);
+    if (e == hipSuccess) e = set_lds<PP, MODE_DEPOSIT, true, 0, false>(bytes);
+    return e;
 }
 
-}  // namespace pic
-
-namespace pic {
-hipError_t PIC_CAT(launch_rho_o, PIC_ORDER)(const KParams &prm, int prec, int species, long long np,
-                                           double *rho, hipStream_t st) {
+hipError_t PIC_NAME(launch_rho)(const KParams &prm, int species, long long np, double *rho,
+                                hipStream_t st) {
     if (np == 0) return hipSuccess;
     dim3 g((unsigned)((np + 255) / 256)), bl(256);
-    if (prec == 0) hipLaunchKernelGGL(k_rho<F64>, g, bl, 0, st, prm, species, rho);
-    else hipLaunchKernelGGL(k_rho<Split>, g, bl, 0, st, prm, species, rho);
+    hipLaunchKernelGGL(k_rho<PP>, g, bl, 0, st, prm, species, rho);
     return hipGetLastError();
 }
+#else
+// fused tiled kernels: PIC_PART 1 the one-workgroup-per-tile form, 2 the
+// persistent (batched) form
+constexpr bool PERS_PART = PIC_PART == 2;
+
+hipError_t PIC_NAME(launch_particles)(const KParams &prm, int form, int mode, int dims, int grid,
+                                      int block, size_t lds, int species, hipStream_t st) {
+    (void)species;
+    if (mode != MODE_FUSED || form != (PERS_PART ? 2 : 1)) return hipErrorInvalidValue;
+    return launch_tiled_dims<PP, MODE_FUSED, PERS_PART>(prm, dims, grid, block, lds, st);
+}
+
+hipError_t PIC_NAME(particles_lds_limit)(int bytes) {
+    hipError_t e = hipSuccess;
+    if (e == hipSuccess) e = set_lds<PP, MODE_FUSED, PERS_PART, 0, false>(bytes);
+    if (e == hipSuccess) e = set_lds<PP, MODE_FUSED, PERS_PART, 2, false>(bytes);
+    if (e == hipSuccess) e = set_lds<PP, MODE_FUSED, PERS_PART, 3, false>(bytes);
+    if (e == hipSuccess) e = set_lds<PP, MODE_FUSED, PERS_PART, 0, true>(bytes);
+    if (e == hipSuccess) e = set_lds<PP, MODE_FUSED, PERS_PART, 2, true>(bytes);
+    if (e == hipSuccess) e = set_lds<PP, MODE_FUSED, PERS_PART, 3, true>(bytes);
+    return e;
+}
+#endif
+
 }  // namespace pic
