@@ -387,3 +387,24 @@ def c4(device="cpu", nboxes=64, l_range=(64, 512), big=(256, 256, 256),
     E, B = zero_fields(box3, device)
     boxes.append(box3); sps.append(sp3); Es.append(E); Bs.append(B)
     return Workload("c4_batched_64x2d_plus_256cube_lognormal", boxes, sps, Es, Bs, 10)
+
+
+def particles_from_positions(box: Box, x, u, w, q: float, m: float, device="cpu",
+                             box_index: int = 0) -> Particles:
+    """A species from explicit positions (cell units, (3, np), each in-cell
+    offset on the 2**-24 lattice so that the split form holds it exactly),
+    momenta (3, np) and weights (np,); for hand-built edge cases."""
+    x = torch.as_tensor(np.asarray(x, dtype=np.float64), device=device).clone()
+    u = torch.as_tensor(np.asarray(u, dtype=np.float64), device=device).clone()
+    w = torch.as_tensor(np.asarray(w, dtype=np.float64), device=device).clone()
+    if box.dim == 2:
+        x[1] = 0.0
+    c = torch.floor(x)
+    off = x - c
+    if not bool(torch.all(off * (1 << 24) == torch.round(off * (1 << 24)))):
+        raise ValueError("offsets must lie on the 2**-24 lattice")
+    ci = c.to(torch.int64)
+    cell = ci[0] + box.n[0] * (ci[1] + box.n[1] * ci[2])
+    return Particles(q, m, x.contiguous(), u.contiguous(), w.contiguous(),
+                     cell.to(torch.int32).contiguous(), off.to(torch.float32).contiguous(),
+                     box_index)

@@ -32,6 +32,14 @@ def rel_l2(a, b):
     return float(np.linalg.norm((a - b).ravel()) / (nb if nb > 0 else 1.0))
 
 
+def node_max_rel(a, b):
+    """max over nodes |a - b| / max |b| (node-wise bound beside rel_l2)."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    mb = np.max(np.abs(b)) if b.size else 0.0
+    return float(np.max(np.abs(a - b)) / (mb if mb > 0 else 1.0)) if b.size else 0.0
+
+
 def periodic_diff(a, b, L):
     """a - b folded into [-L/2, L/2) per row (positions in cell units)."""
     d = np.asarray(a) - np.asarray(b)
@@ -80,6 +88,18 @@ class GpuRun:
 
     def check(self):
         pic.pic_check(self.ctx)
+
+    def energy(self, b=0):
+        """(field energy, kinetic energy of all species of box b) from the
+        library's FP64 device reductions."""
+        out = pic.pic_energy(self.ctx, self.f, self.sp, b).cpu().numpy()
+        return float(out[0] + out[1]), float(np.sum(out[2:]))
+
+    def rho_np(self, b=0):
+        box = self.wl.boxes[b]
+        r = torch.zeros(box.ncells, dtype=torch.float64, device="cuda")
+        pic.pic_deposit_rho(self.ctx, self.sp, b, r)
+        return r.cpu().numpy()
 
     def fields_np(self, b=0):
         box = self.wl.boxes[b]
