@@ -412,6 +412,10 @@ def main():
     ap.add_argument("--tile32", type=int, nargs=3, default=None)
     ap.add_argument("--sort-every", type=int, default=None)
     ap.add_argument("--cell-order", type=int, default=None)
+    ap.add_argument("--stride", type=int, default=None, help="FP32 lane stride override")
+    ap.add_argument("--cell-order64", type=int, default=None)
+    ap.add_argument("--stride64", type=int, default=None)
+    ap.add_argument("--sort-every64", type=int, default=None)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -436,6 +440,14 @@ def main():
         c32 = dataclasses.replace(c32, sort_every=args.sort_every)
     if args.cell_order is not None:
         c32 = dataclasses.replace(c32, cell_order=args.cell_order)
+    if args.stride is not None:
+        c32 = dataclasses.replace(c32, lane_stride=args.stride)
+    if args.cell_order64 is not None:
+        c64 = dataclasses.replace(c64, cell_order=args.cell_order64)
+    if args.stride64 is not None:
+        c64 = dataclasses.replace(c64, lane_stride=args.stride64)
+    if args.sort_every64 is not None:
+        c64 = dataclasses.replace(c64, sort_every=args.sort_every64)
     t0 = time.time()
     wl = pi.c5("cuda")
     torch.cuda.synchronize()
@@ -498,7 +510,8 @@ def main():
         v64 = r64["np"] * 1e3 / r64["ms_step"]
         out["fp64_plain"] = {"value": v64, "ms_per_step": r64["ms_step"],
                              "breakdown_ms": {"advance": r64["ms_advance"], "sort": r64["ms_sort"],
-                                              "fdtd": r64["ms_fdtd"]},
+                                              "fdtd": r64["ms_fdtd"],
+                                              "advance_per_step": r64["kernel_ms_steps"]},
                              "config": launch_config(c64), "sort_every": c64.sort_every,
                              "autotuned": tuned64}
         out["speedup_fp32_batched_vs_fp64_plain"] = value / v64

@@ -130,9 +130,16 @@ typedef struct {
                             pooling of the deposit at lane_stride 1).  3: by
                             the cell lx + tx*(ly + ty*lz) alone, ties stable
                             (restores the cell-major order that lane_stride
-                            4 spreads over distinct cells).  1..3 apply when
-                            tile id and cell fit a 31-bit key.
-                            0 = default: 2 for BATCHED, else -1. */
+                            4 spreads over distinct cells).  4: rank-major:
+                            by the rank of a particle among its cell's
+                            particles (0..15, ties in cell order), so that
+                            consecutive particles of one rank sit in
+                            consecutive cells whatever the per-cell counts
+                            (for lane_stride 1).  1..4 apply when tile id
+                            and cell fit a 31-bit key.
+                            0 = default: 2 for BATCHED, else -1.  The DPP
+                            quad pooling of the deposit runs only with
+                            lane_stride 1 and order 2. */
     int32_t quad_spread; /* TILED/BATCHED at lane_stride 1: 1 = the 16 quads
                             of a wave are taken ceil(nquads/16) quads apart
                             in a species' tile range instead of in a row, so
@@ -144,6 +151,14 @@ typedef struct {
                             axes where it fits (default); -1 = no margin
                             (particles out of their tile since the sort take
                             the global path; smaller LDS stage). */
+    int32_t pusher;      /* 0 = relativistic Boris (default); 1 = the pusher
+                            of Vay (Phys. Plasmas 15, 056701, 2008), exact
+                            for the E x B drift at any speed */
+    int32_t gather;      /* 0 = every field component gathered with order-n
+                            shapes on all axes (default); 1 = Galerkin form:
+                            order n - 1 along each axis on which the
+                            component sits at half-integer points (order 0 =
+                            the nearest node) */
 } pic_tuning;
 
 typedef struct {
@@ -265,10 +280,148 @@ pic_status pic_div_edge(pic_ctx *ctx, int32_t box, double *const v[3],
  *   out[2 + s] = sum over the particles of species s of w m (gamma - 1),
  *            gamma - 1 evaluated as u.u / (1 + gamma); 0 for a species of
  *            another box.
- * Summation order across workgroups is unspecified (FP64 atomics).
- * Errors: PIC_ERR_ARG (bad box, NULL out or field pointer, bad species). */
+ * Deterministic: per-workgroup partial sums (in context scratch, allocated
+ * on first use) are added in a fixed order.  At most 16 species.
+ * Errors: PIC_ERR_ARG (bad box, NULL out or field pointer, bad species,
+ * nsp > 16), PIC_ERR_OOM (scratch). */
 pic_status pic_energy(pic_ctx *ctx, const pic_fields *f, const pic_species *sp,
                       int32_t nsp, int32_t box, double *out);
+
+
+/* Decomposition of one periodic box into slabs along z, the boxes of this
+ * context: the domain decomposition of the paper's multi-GPU runs (Sec.
+ * III.B, Fig. 2), held on one GPU.  Box s of the context is slab s (z
+ * order, periodic neighbours): it owns global layers [z0_s, z0_s + nz_s)
+ * and stores them at local z in [guard, guard + nz_s), with `guard` layers
+ * below and above; n[2] of box s = nz_s + 2 guard.  All slabs share dim,
+ * nx, ny, dx, dt and order; guard >= 3 (the Yee update and the widest
+ * order-3 stencils stay valid with 3) and nz_s >= 2 guard
+ * (PIC_ERR_ARG otherwise).  Particles live in the interiors; field and
+ * particle arrays are the caller's, as for any box.  One step is:
+ *   pic_slab_fill_guards; [pic_sort_tiles]; pic_advance (all slabs in one
+ *   launch); pic_slab_reduce_j; pic_fdtd_step; pic_slab_migrate; and a
+ *   pic_sort_tiles before the next tiled particle update whenever counts
+ *   changed.
+ * Results equal those of the undivided box up to the order of the J sums.
+ *
+ * pic_slab_fill_guards: E and B guard layers <- the owning neighbour's
+ * interior layers (before the gather). */
+pic_status pic_slab_fill_guards(pic_ctx *ctx, pic_fields *f, int32_t guard);
+
+/* pic_slab_reduce_j: every guard layer's J is added to the neighbour
+ * interior layer it covers (pulled by the interior, deterministic), then
+ * the complete interior J is copied back into the guards (after the
+ * deposit, before the Yee update). */
+pic_status pic_slab_reduce_j(pic_ctx *ctx, pic_fields *f, int32_t guard);
+
+/* pic_slab_migrate: particles whose position left their slab's interior
+ * (they are at most one cell into a guard) move to the neighbour slab's
+ * arrays, z shifted into its frame.  sp: nsp = nslab x kinds species given
+ * slab-major (sp[i].box == i / kinds; kind k of every slab is one particle
+ * kind), each with its current count np; cap[i] (host) = capacity of its
+ * arrays in particles.  Each species keeps its stayers in order, then the
+ * arrivals from the slab below, then from above.  np_out[i] (host) gets the
+ * new counts; the call waits for the stream once (to learn the counts).
+ * PIC_ERR_ARG if a count would exceed its capacity (nothing is changed). */
+pic_status pic_slab_migrate(pic_ctx *ctx, pic_species *sp, int32_t nsp, int32_t guard,
+                            const int64_t *cap, int64_t *np_out);
+
+/* ---- Laser-plasma boundaries (the steps around the periodic core of a
+ * laser-wakefield run, paper Abstract and Sec. III.A: a laser enters from an
+ * antenna, the fields are absorbed at the ends of z, and the frame moves
+ * with the laser).  z is the laser axis; x and y stay periodic. */
+
+/* Absorbing layers of `cells` cells at both ends of z of box `box` (in the
+ * frame of the moving window, see pic_window_shift): Maxwell's equations
+ * with an electric and an equal magnetic conductivity sigma(d) = sigma_max
+ * (d / cells)^power at depth d into a layer, which match the vacuum
+ * impedance, so a wave at normal incidence enters without reflection in
+ * the continuum limit and decays as exp(-integral sigma dz).  pic_fdtd_step
+ * then integrates the decay of each sub-step exactly: F <- exp(-sigma tau) F
+ * + (1 - exp(-sigma tau)) / sigma * (curl source), sigma at each component's
+ * own Yee point.  cells = 0 removes the layers.  PIC_ERR_ARG unless
+ * 0 <= 2 cells <= n_z, sigma_max >= 0, 0 <= power <= 8.  Waits for the
+ * stream (set-up call). */
+pic_status pic_set_absorber(pic_ctx *ctx, int32_t box, int32_t cells, double sigma_max,
+                            int32_t power);
+
+/* Laser antenna: a current sheet at the E_x points of cell layer k of the
+ * window frame, K_x(x, y, t) = -2 E0 exp(-r^2 / waist^2) exp(-((t - t0) /
+ * tau)^2) sin(omega (t - t0)), r from (x0, y0) (cell units times dx); a
+ * current sheet K radiates E = -K / 2 on both sides, so each emitted wave
+ * has amplitude E0 (the backward one is for the absorbing layer).  Added
+ * as K / dz into J_x of that layer: call after pic_deposit_J (or
+ * pic_advance) and before pic_fdtd_step, with t = the time of that J
+ * (t^(n+1/2) = (n + 1/2) dt). */
+typedef struct {
+    int32_t k;           /* window-frame cell layer of the sheet */
+    double E0;           /* emitted field amplitude */
+    double omega;        /* angular frequency */
+    double waist;        /* 1/e field radius */
+    double x0, y0;       /* centre of the spot */
+    double t0, tau;      /* centre and 1/e half-length of the envelope */
+} pic_antenna;
+pic_status pic_antenna_add(pic_ctx *ctx, pic_fields *f, int32_t box, const pic_antenna *an,
+                           double t);
+
+/* Moving window: the frame of box `box` advances one cell along +z.  The
+ * field arrays are circular in z: the frame's layer 0 sits at array layer
+ * zoff (pic_window_offset), and a shift zeroes E and B of the array layer
+ * that leaves the frame's bottom (it becomes the new top layer), removes
+ * the particles in it (the others keep their order) and advances zoff by
+ * one; no field data moves.  inject[i] (species i of the box) are new
+ * particles for the new top layer, positions in the window frame (FP64: z
+ * in [n_z - 1, n_z); split: cell ids of that layer), appended after the
+ * kept ones (np 0 for none; same precision and arrays as sp[i]).  cap[i]
+ * (host) = capacity of sp[i]'s arrays; np_out[i] (host) = the new counts
+ * (species of other boxes unchanged).  Waits for the stream to learn the
+ * counts; PIC_ERR_ARG if a count would exceed its capacity.  Positions
+ * of all particles stay in array coordinates, so the particle kernels need
+ * no change; a pic_sort_tiles must precede the next tiled update. */
+pic_status pic_window_shift(pic_ctx *ctx, pic_fields *f, pic_species *sp, int32_t nsp,
+                            int32_t box, const pic_species *inject, const int64_t *cap,
+                            int64_t *np_out);
+
+/* Array layer of the window frame's layer 0 of box `box`. */
+pic_status pic_window_offset(pic_ctx *ctx, int32_t box, int32_t *zoff);
+
+/* ---- Electrostatic variant (the paper's codes include an electrostatic
+ * PIC solver beside the electromagnetic one, Sec. II and IV).  One ES step
+ * is pic_es_solve then pic_es_push; B is not used.
+ *
+ * pic_es_solve: charge density rho of the species of box `box` (as
+ * pic_deposit_rho), its mean removed (a neutralising background), the
+ * discrete periodic Poisson equation -div grad phi = rho - <rho> solved by
+ * conjugate gradients from phi = 0 with the 7-point Yee Laplacian (5-point
+ * in 2D) until |r| <= tol |rho - <rho>| (checked every 16 iterations), the
+ * mean of phi removed, and E = -grad phi written at the Yee E points
+ * (E_x(i+1/2) = -(phi(i+1) - phi(i)) / dx ...) into f->E of the box, so
+ * div E = rho - <rho> to the tolerance.  phi: DEVICE array of the box's
+ * ncells doubles (caller-owned, overwritten).  *iters_out / *res_out (host,
+ * may be NULL): iterations and final relative residual.  Waits for the
+ * stream every 16 iterations.  PIC_ERR_STATE if max_iter is reached first
+ * (E is still written). */
+pic_status pic_es_solve(pic_ctx *ctx, const pic_species *sp, int32_t nsp, int32_t box,
+                        pic_fields *f, double *phi, double tol, int32_t max_iter,
+                        int32_t *iters_out, double *res_out);
+
+/* pic_es_push: every particle gathers E at x^n (order-n shapes on each
+ * component's Yee points, as pic_gather_push), takes the Boris step with
+ * B = 0 (u += q E dt / m), advances x^(n+1) = x^n + dt u / (gamma dx) and
+ * wraps; no current.  One thread per particle (no sort needed; a later
+ * tiled call needs pic_sort_tiles again). */
+pic_status pic_es_push(pic_ctx *ctx, const pic_fields *f, pic_species *sp, int32_t nsp);
+
+/* In-situ reduction (a diagnostic beside the step, the kind of streaming
+ * analysis the paper's codes run in place of full output, Sec. IV):
+ * per-layer moments along z of every species of box `box`, in the frame of
+ * the moving window (layer (k - zoff) mod n_z of array layer k):
+ * out[(s n_z + k) 5 + q], q = 0 sum w, 1..3 sum w u_d, 4 sum w m (gamma - 1)
+ * (gamma - 1 = u.u / (1 + gamma)).  out: DEVICE array of 5 n_z nsp doubles
+ * (caller-owned, overwritten; zero for species of other boxes).  FP64
+ * atomics (summation order unspecified). */
+pic_status pic_slice_moments(pic_ctx *ctx, const pic_species *sp, int32_t nsp, int32_t box,
+                             double *out);
 
 /* Wait for the stream and report the first device-side error (then clear). */
 pic_status pic_check(pic_ctx *ctx);

@@ -44,6 +44,16 @@ class Species(C.Structure):
                 ("x", C.c_void_p * 3), ("u", C.c_void_p * 3), ("w", C.c_void_p)]
 
 
+class Absorber(C.Structure):
+    _fields_ = [("cells", C.c_int32), ("sigma_max", C.c_double), ("power", C.c_int32)]
+
+
+class Antenna(C.Structure):
+    _fields_ = [("k", C.c_int32), ("E0", C.c_double), ("omega", C.c_double),
+                ("waist", C.c_double), ("x0", C.c_double), ("y0", C.c_double),
+                ("t0", C.c_double), ("tau", C.c_double)]
+
+
 _P = C.c_void_p
 _D = C.c_double
 _I = C.c_int32
@@ -79,6 +89,21 @@ def lib():
         L.orc_stable_perm.argtypes = [C.c_int64, _P, _P]
         L.orc_quad_order.argtypes = [C.c_int64, _P, _I, _P]
         L.orc_tile_cell_keys.argtypes = [C.POINTER(Grid), _P, _I, C.POINTER(Species), _P]
+        L.orc_absorber_sigma.argtypes = [C.POINTER(Absorber), _D, _D]
+        L.orc_absorber_sigma.restype = _D
+        L.orc_fdtd_step_absorb.argtypes = [C.POINTER(Grid), _P, _P, _P, C.POINTER(Absorber), _D]
+        L.orc_antenna_add.argtypes = [C.POINTER(Grid), _P, C.POINTER(Antenna), _D]
+        L.orc_window_shift_fields.argtypes = [C.POINTER(Grid), _P, _P]
+        L.orc_window_shift_particles.argtypes = [C.POINTER(Grid), C.POINTER(Species)]
+        L.orc_window_shift_particles.restype = C.c_int64
+        L.orc_es_field.argtypes = [C.POINTER(Grid), _P, _P]
+        L.orc_vay.argtypes = [_D, _D, _D, _P, _P, _P]
+        L.orc_slice_moments.argtypes = [C.POINTER(Grid), C.POINTER(Species), _I, _P]
+        L.orc_rank_major.argtypes = [C.c_int64, _P, _I, _I, _P]
+        L.orc_gather_galerkin.argtypes = [C.POINTER(Grid), _P, _P, _P, _P, _P]
+        L.orc_particles_step_opts.argtypes = [C.POINTER(Grid), _P, _P, _P, C.POINTER(Species), _I,
+                                              _I, _I]
+        L.orc_es_particles_step.argtypes = [C.POINTER(Grid), _P, C.POINTER(Species), _I]
         _lib = L
     return _lib
 
@@ -270,3 +295,134 @@ def stable_sort(key, nkeys):
     lib().orc_stable_sort(n, key.ctypes.data, nkeys, perm.ctypes.data,
                           count.ctypes.data, offset.ctypes.data)
     return perm, count, offset
+
+
+# ------------------------------------------------------------------ boundaries
+
+def absorber(cells, sigma_max, power=3) -> Absorber:
+    a = Absorber()
+    a.cells, a.sigma_max, a.power = int(cells), float(sigma_max), int(power)
+    return a
+
+
+def absorber_sigma(a: Absorber, z, nz):
+    return lib().orc_absorber_sigma(C.byref(a), float(z), float(nz))
+
+
+def fdtd_step_absorb(g: Grid, E, B, J, a: Absorber, zoff=0.0):
+    Ef, Bf, Jf = _FieldPtrs(_rows(E)), _FieldPtrs(_rows(B)), _FieldPtrs(_rows(J))
+    lib().orc_fdtd_step_absorb(C.byref(g), Ef.ptr, Bf.ptr, Jf.ptr, C.byref(a), float(zoff))
+
+
+def antenna(k, E0, omega, waist, x0, y0, t0, tau) -> Antenna:
+    an = Antenna()
+    an.k, an.E0, an.omega, an.waist = int(k), float(E0), float(omega), float(waist)
+    an.x0, an.y0, an.t0, an.tau = float(x0), float(y0), float(t0), float(tau)
+    return an
+
+
+def antenna_add(g: Grid, J, an: Antenna, t):
+    lib().orc_antenna_add(C.byref(g), _FieldPtrs(_rows(J)).ptr, C.byref(an), float(t))
+
+
+def window_shift_fields(g: Grid, E, B):
+    lib().orc_window_shift_fields(C.byref(g), _FieldPtrs(_rows(E)).ptr, _FieldPtrs(_rows(B)).ptr)
+
+
+def window_shift_particles(g: Grid, sp):
+    """Shifts and compacts ``sp`` (x, u, w arrays of capacity >= np) in place;
+    returns the new count.  ``sp.np`` (if present) is not changed."""
+    st = _species_struct(sp)
+    return int(lib().orc_window_shift_particles(C.byref(g), C.byref(st)))
+
+
+# ------------------------------------------------------------------ electrostatic
+
+def poisson_periodic(g: Grid, rho):
+    """phi solving the discrete periodic Poisson equation div grad phi =
+    -(rho - mean rho) with the Yee differences (the 7-point Laplacian; 5
+    points in 2D), mean of phi zero.  Exact, by the discrete Fourier
+    transform: each mode of the Laplacian has eigenvalue -sum_d (2 - 2
+    cos(2 pi k_d / n_d)) / dx_d^2."""
+    n = [int(g.n[d]) for d in range(3)]
+    r = np.asarray(rho, dtype=np.float64).reshape(n[2], n[1], n[0])
+    rh = np.fft.fftn(r - r.mean())
+    lam = np.zeros((n[2], n[1], n[0]))
+    for d, ax in ((0, 2), (1, 1), (2, 0)):
+        if g.dim == 2 and d == 1:
+            continue
+        k = np.arange(n[d])
+        l1 = (2.0 - 2.0 * np.cos(2.0 * np.pi * k / n[d])) / (g.dx[d] ** 2)
+        shape = [1, 1, 1]
+        shape[ax] = n[d]
+        lam = lam + l1.reshape(shape)
+    lam[0, 0, 0] = 1.0
+    ph = rh / lam
+    ph[0, 0, 0] = 0.0
+    return np.ascontiguousarray(np.real(np.fft.ifftn(ph)).reshape(-1))
+
+
+def es_field(g: Grid, phi):
+    E = np.zeros((3, int(np.prod([g.n[d] for d in range(3)]))))
+    lib().orc_es_field(C.byref(g), _f64(np.ascontiguousarray(phi)).ctypes.data,
+                       _FieldPtrs(_rows(E)).ptr)
+    return E
+
+
+def es_particles_step(g: Grid, E, species):
+    Ef = _FieldPtrs(_rows(E))
+    arr = (Species * len(species))(*[_species_struct(s) for s in species])
+    lib().orc_es_particles_step(C.byref(g), Ef.ptr, arr, len(species))
+
+
+def es_step(g: Grid, species, ncells):
+    """One electrostatic step: rho of the species, Poisson, E = -grad phi,
+    particle update.  Returns (rho, phi, E) of the step's start."""
+    r = rho(g, species, ncells)
+    phi = poisson_periodic(g, r)
+    E = es_field(g, phi)
+    es_particles_step(g, E, species)
+    return r, phi, E
+
+
+# ------------------------------------------------------------------ variants
+
+def vay(q, m, dt, Ep, Bp, u):
+    u = np.array(u, dtype=np.float64)
+    Ep = np.ascontiguousarray(Ep, dtype=np.float64)
+    Bp = np.ascontiguousarray(Bp, dtype=np.float64)
+    lib().orc_vay(q, m, dt, Ep.ctypes.data, Bp.ctypes.data, u.ctypes.data)
+    return u
+
+
+def gather_galerkin(g: Grid, E, B, xi):
+    Ef, Bf = _FieldPtrs(_rows(E)), _FieldPtrs(_rows(B))
+    x = np.ascontiguousarray(xi, dtype=np.float64)
+    Ep, Bp = np.zeros(3), np.zeros(3)
+    lib().orc_gather_galerkin(C.byref(g), Ef.ptr, Bf.ptr, x.ctypes.data, Ep.ctypes.data,
+                              Bp.ctypes.data)
+    return Ep, Bp
+
+
+def particles_step_opts(g: Grid, E, B, J, species, pusher=0, gather=0):
+    Ef, Bf, Jf = _FieldPtrs(_rows(E)), _FieldPtrs(_rows(B)), _FieldPtrs(_rows(J))
+    arr = (Species * len(species))(*[_species_struct(s) for s in species])
+    lib().orc_particles_step_opts(C.byref(g), Ef.ptr, Bf.ptr, Jf.ptr, arr, len(species),
+                                  int(pusher), int(gather))
+
+
+def slice_moments(g: Grid, sp, zoff=0):
+    """(n_z, 5): per z layer sum w, w u_x, w u_y, w u_z, w m (gamma - 1)."""
+    out = np.zeros(5 * int(g.n[2]))
+    st = _species_struct(sp)
+    lib().orc_slice_moments(C.byref(g), C.byref(st), int(zoff), out.ctypes.data)
+    return out.reshape(-1, 5)
+
+
+def rank_major(key, cbits, rbits=4):
+    """Rank-major within-tile order of (tile, cell) keys (int64 array)."""
+    k = np.ascontiguousarray(key, dtype=np.int64)
+    perm = np.zeros(k.shape[0], dtype=np.int32)
+    lib().orc_rank_major(k.shape[0], k.ctypes.data, int(cbits), int(rbits), perm.ctypes.data)
+    return perm
+

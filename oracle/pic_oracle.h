@@ -106,6 +106,68 @@ double orc_field_energy(const orc_grid *g, double *const E[3],
                         double *const B[3]);
 double orc_kinetic_energy(const orc_species *sp);
 
+/* Absorbing layers of `cells` cells at both z ends with equal electric and
+ * magnetic conductivity sigma(d) = sigma_max (d / cells)^power at depth d. */
+typedef struct {
+    int32_t cells;
+    double sigma_max;
+    int32_t power;
+} orc_absorber;
+
+/* Conductivity at height z (cell units) of a box nz cells long. */
+double orc_absorber_sigma(const orc_absorber *a, double z, double nz);
+
+/* Yee step (B half, E full, B half) with the absorbing layers; each
+ * sub-step integrates the conductive decay exactly.  The layers sit at the
+ * window-frame ends: a component at array height z has frame height
+ * (z - zoff) mod nz (zoff = 0 without a moving window). */
+void orc_fdtd_step_absorb(const orc_grid *g, double *E[3], double *B[3], double *const J[3],
+                          const orc_absorber *a, double zoff);
+
+/* Laser antenna: a current sheet at the E_x points of cell layer k. */
+typedef struct {
+    int32_t k;        /* cell layer of the sheet */
+    double E0;        /* emitted field amplitude */
+    double omega;     /* angular frequency */
+    double waist;     /* 1/e field radius */
+    double x0, y0;    /* centre */
+    double t0, tau;   /* centre and 1/e half-length of the envelope in time */
+} orc_antenna;
+
+/* Adds the antenna's current at time t into J[0]. */
+void orc_antenna_add(const orc_grid *g, double *J[3], const orc_antenna *an, double t);
+
+/* Moving window by one cell along +z: fields shift toward -z with a zero
+ * top layer; particles shift and those leaving are removed (order kept). */
+void orc_window_shift_fields(const orc_grid *g, double *E[3], double *B[3]);
+int64_t orc_window_shift_particles(const orc_grid *g, orc_species *sp);
+
+/* Electrostatic variant: E = -grad phi at the Yee E points; the particle
+ * update in E alone (gather, Boris with B = 0, advance, wrap; no deposit). */
+void orc_es_field(const orc_grid *g, const double *phi, double *E[3]);
+void orc_es_particles_step(const orc_grid *g, double *const E[3], orc_species *sp, int32_t nsp);
+
+/* Variants: the relativistic pusher of Vay (2008); the Galerkin gather
+ * (order lowered by one along each axis where the component is at
+ * half-integer points; order 0 = nearest node); the particle step with
+ * pusher (0 Boris, 1 Vay) and gather (0 default, 1 Galerkin) chosen. */
+void orc_vay(double q, double m, double dt, const double Ep[3], const double Bp[3], double u[3]);
+void orc_gather_galerkin(const orc_grid *g, double *const E[3], double *const B[3],
+                         const double xi[3], double Ep[3], double Bp[3]);
+void orc_particles_step_opts(const orc_grid *g, double *const E[3], double *const B[3],
+                             double *J[3], orc_species *sp, int32_t nsp, int32_t pusher,
+                             int32_t gather);
+
+/* Per-layer moments along z (window frame, zoff as the moving window):
+ * out[5 k + q] += sum over the layer's particles of w, w u_x, w u_y, w u_z,
+ * w m (gamma - 1). */
+void orc_slice_moments(const orc_grid *g, const orc_species *sp, int32_t zoff, double *out);
+
+/* Rank-major order inside each tile of a (tile, cell) key: by rank of a
+ * particle within its cell (capped at 2^rbits - 1), ties in cell order.  A
+ * layout choice of the GPU sort (pic_tuning.cell_order 4). */
+void orc_rank_major(int64_t np, const int64_t *key, int32_t cbits, int32_t rbits, int32_t *perm);
+
 /* Tile id of every particle, tile = cell / tile[d] per axis (partial tiles at
  * the high end allowed), id = tx + ntx*(ty + nty*tz). */
 void orc_tile_keys(const orc_grid *g, const int32_t tile[3],

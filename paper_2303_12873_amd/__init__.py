@@ -26,7 +26,9 @@ PIC_FP64, PIC_FP32_SPLIT = 0, 1
 PIC_KERNEL_DIRECT, PIC_KERNEL_TILED, PIC_KERNEL_BATCHED = 0, 1, 2
 
 EXPORTED = ["pic_init", "pic_sort_tiles", "pic_gather_push", "pic_deposit_J", "pic_advance",
-            "pic_fdtd_step", "pic_step", "pic_deposit_rho", "pic_div_edge", "pic_energy", "pic_check",
+            "pic_fdtd_step", "pic_step", "pic_deposit_rho", "pic_div_edge", "pic_energy", "pic_slab_fill_guards", "pic_slab_reduce_j",
+            "pic_slab_migrate", "pic_set_absorber", "pic_antenna_add", "pic_window_shift",
+            "pic_window_offset", "pic_es_solve", "pic_es_push", "pic_slice_moments", "pic_check",
             "pic_free", "pic_status_str", "pic_last_error", "pic_device_cus", "pic_set_timing",
             "pic_kernel_ms"]
 
@@ -40,7 +42,8 @@ class pic_box_desc(C.Structure):
 class pic_tuning(C.Structure):
     _fields_ = [("kernel", C.c_int32), ("block", C.c_int32), ("chunk", C.c_int32),
                 ("wg_per_cu", C.c_int32), ("lane_stride", C.c_int32), ("pad", C.c_int32),
-                ("cell_order", C.c_int32), ("quad_spread", C.c_int32), ("margin", C.c_int32)]
+                ("cell_order", C.c_int32), ("quad_spread", C.c_int32), ("margin", C.c_int32),
+                ("pusher", C.c_int32), ("gather", C.c_int32)]
 
 
 class pic_fields(C.Structure):
@@ -51,6 +54,12 @@ class pic_species(C.Structure):
     _fields_ = [("np", C.c_int64), ("q", C.c_double), ("m", C.c_double), ("box", C.c_int32),
                 ("x", C.c_void_p * 3), ("cell", C.c_void_p), ("off", C.c_void_p * 3),
                 ("u", C.c_void_p * 3), ("w", C.c_void_p)]
+
+
+class pic_antenna(C.Structure):
+    _fields_ = [("k", C.c_int32), ("E0", C.c_double), ("omega", C.c_double),
+                ("waist", C.c_double), ("x0", C.c_double), ("y0", C.c_double),
+                ("t0", C.c_double), ("tau", C.c_double)]
 
 
 class PicError(RuntimeError):
@@ -79,6 +88,18 @@ def lib():
         L.pic_deposit_rho.argtypes = [P, C.POINTER(pic_species), I, I, P]
         L.pic_div_edge.argtypes = [P, I, P, P]
         L.pic_energy.argtypes = [P, C.POINTER(pic_fields), C.POINTER(pic_species), I, I, P]
+        L.pic_slab_fill_guards.argtypes = [P, C.POINTER(pic_fields), I]
+        L.pic_slab_reduce_j.argtypes = [P, C.POINTER(pic_fields), I]
+        L.pic_slab_migrate.argtypes = [P, C.POINTER(pic_species), I, I, P, P]
+        L.pic_set_absorber.argtypes = [P, I, I, C.c_double, I]
+        L.pic_antenna_add.argtypes = [P, C.POINTER(pic_fields), I, C.POINTER(pic_antenna), C.c_double]
+        L.pic_window_shift.argtypes = [P, C.POINTER(pic_fields), C.POINTER(pic_species), I, I,
+                                       C.POINTER(pic_species), P, P]
+        L.pic_window_offset.argtypes = [P, I, C.POINTER(C.c_int32)]
+        L.pic_es_solve.argtypes = [P, C.POINTER(pic_species), I, I, C.POINTER(pic_fields), P,
+                                   C.c_double, I, C.POINTER(C.c_int32), C.POINTER(C.c_double)]
+        L.pic_es_push.argtypes = [P, C.POINTER(pic_fields), C.POINTER(pic_species), I]
+        L.pic_slice_moments.argtypes = [P, C.POINTER(pic_species), I, I, P]
         L.pic_check.argtypes = [P]
         L.pic_free.argtypes = [P]
         L.pic_status_str.argtypes = [I]
@@ -160,9 +181,14 @@ class DeviceSpecies:
     x: Optional[torch.Tensor] = None       # FP64: (3, np)
     cell: Optional[torch.Tensor] = None    # split: (np,) int32
     off: Optional[torch.Tensor] = None     # split: (3, np) float32
+    count: Optional[int] = None            # particles in use (None: all of the arrays)
 
     @property
     def np(self) -> int:
+        return int(self.w.shape[0]) if self.count is None else int(self.count)
+
+    @property
+    def capacity(self) -> int:
         return int(self.w.shape[0])
 
     def c(self) -> pic_species:
@@ -182,19 +208,28 @@ class DeviceSpecies:
         return s
 
 
-def make_species(p, precision: int, box: int = None, device="cuda") -> DeviceSpecies:
+def make_species(p, precision: int, box: int = None, device="cuda",
+                 capacity: Optional[int] = None) -> DeviceSpecies:
     """Device copy of a ``pic_inputs.Particles`` in the requested form (always
-    new storage: the kernels update it in place)."""
+    new storage: the kernels update it in place).  ``capacity`` > np leaves
+    room for particles arriving later (pic_slab_migrate)."""
     b = p.box if box is None else box
+    n = p.np
+    cap = n if capacity is None else int(capacity)
+    if cap < n:
+        raise ValueError("capacity below the particle count")
 
     def cp(t, dt):
-        return t.to(device=device, dtype=dt, copy=True).contiguous()
+        out = torch.zeros((*t.shape[:-1], cap), dtype=dt, device=device)
+        out[..., :n].copy_(t)
+        return out.contiguous()
 
+    cnt = None if capacity is None else n
     if precision == PIC_FP64:
         return DeviceSpecies(p.q, p.m, b, precision, cp(p.u, torch.float64), cp(p.w, torch.float64),
-                             x=cp(p.x, torch.float64))
+                             x=cp(p.x, torch.float64), count=cnt)
     return DeviceSpecies(p.q, p.m, b, precision, cp(p.u, torch.float32), cp(p.w, torch.float32),
-                         cell=cp(p.cell, torch.int32), off=cp(p.off, torch.float32))
+                         cell=cp(p.cell, torch.int32), off=cp(p.off, torch.float32), count=cnt)
 
 
 def _species_array(species: Sequence[DeviceSpecies]):
@@ -213,7 +248,8 @@ def _ptr_array(ts):
 
 def pic_init(boxes, precision: int, stream=None, kernel: Optional[int] = None, block: int = 0,
              chunk: int = 0, wg_per_cu: int = 0, lane_stride: int = 0, pad: int = 0,
-             cell_order: int = 0, quad_spread: int = 0, margin: int = 0):
+             cell_order: int = 0, quad_spread: int = 0, margin: int = 0, pusher: int = 0,
+             gather: int = 0):
     """boxes: objects with dim, n, dx, dt, order, tile (``pic_inputs.Box``).
     Returns an opaque context handle (int)."""
     descs = (pic_box_desc * len(boxes))()
@@ -231,7 +267,7 @@ def pic_init(boxes, precision: int, stream=None, kernel: Optional[int] = None, b
         base += b.ncells
     tun = None
     if (kernel is not None or block or chunk or wg_per_cu or lane_stride or pad or cell_order
-            or quad_spread or margin):
+            or quad_spread or margin or pusher or gather):
         tun = pic_tuning()
         tun.kernel = (PIC_KERNEL_TILED if precision == PIC_FP64 else PIC_KERNEL_BATCHED) \
             if kernel is None else kernel
@@ -241,6 +277,8 @@ def pic_init(boxes, precision: int, stream=None, kernel: Optional[int] = None, b
         tun.cell_order = cell_order
         tun.quad_spread = quad_spread
         tun.margin = margin
+        tun.pusher = pusher
+        tun.gather = gather
     if stream is None:
         stream = torch.cuda.current_stream().cuda_stream
     h = C.c_void_p()
@@ -301,6 +339,89 @@ def pic_energy(ctx, fields: DeviceFields, species, box: int = 0, out: torch.Tens
     f = fields.c()
     _check(lib().pic_energy(ctx, C.byref(f), _species_array(species), len(species), box,
                             _ptr(out)))
+    return out
+
+
+def pic_slab_fill_guards(ctx, fields: DeviceFields, guard: int):
+    f = fields.c()
+    _check(lib().pic_slab_fill_guards(ctx, C.byref(f), guard))
+
+
+def pic_slab_reduce_j(ctx, fields: DeviceFields, guard: int):
+    f = fields.c()
+    _check(lib().pic_slab_reduce_j(ctx, C.byref(f), guard))
+
+
+def pic_slab_migrate(ctx, species, guard: int):
+    """Moves particles between slabs; updates each species' count in place
+    and returns the new counts."""
+    cap = (C.c_int64 * len(species))(*[s.capacity for s in species])
+    out = (C.c_int64 * len(species))()
+    _check(lib().pic_slab_migrate(ctx, _species_array(species), len(species), guard,
+                                  C.cast(cap, C.c_void_p), C.cast(out, C.c_void_p)))
+    for s, n in zip(species, out):
+        s.count = int(n)
+    return [int(n) for n in out]
+
+
+def pic_set_absorber(ctx, box: int, cells: int, sigma_max: float, power: int = 3):
+    _check(lib().pic_set_absorber(ctx, box, cells, sigma_max, power))
+
+
+def pic_antenna_add(ctx, fields: DeviceFields, box: int, k: int, E0: float, omega: float,
+                    waist: float, x0: float, y0: float, t0: float, tau: float, t: float):
+    an = pic_antenna()
+    an.k, an.E0, an.omega, an.waist = k, E0, omega, waist
+    an.x0, an.y0, an.t0, an.tau = x0, y0, t0, tau
+    f = fields.c()
+    _check(lib().pic_antenna_add(ctx, C.byref(f), box, C.byref(an), t))
+
+
+def pic_window_shift(ctx, fields: DeviceFields, species, box: int, inject):
+    """``inject``: one DeviceSpecies (or None) per species; updates counts in
+    place and returns them."""
+    empty = pic_species()
+    inj = (pic_species * max(1, len(species)))(
+        *[(s.c() if s is not None else empty) for s in inject])
+    cap = (C.c_int64 * len(species))(*[s.capacity for s in species])
+    out = (C.c_int64 * len(species))()
+    f = fields.c()
+    _check(lib().pic_window_shift(ctx, C.byref(f), _species_array(species), len(species), box,
+                                  inj, C.cast(cap, C.c_void_p), C.cast(out, C.c_void_p)))
+    for s, n in zip(species, out):
+        s.count = int(n)
+    return [int(n) for n in out]
+
+
+def pic_window_offset(ctx, box: int = 0) -> int:
+    z = C.c_int32()
+    _check(lib().pic_window_offset(ctx, box, C.byref(z)))
+    return int(z.value)
+
+
+def pic_es_solve(ctx, species, box: int, fields: DeviceFields, phi: torch.Tensor,
+                 tol: float = 1e-12, max_iter: int = 5000):
+    """Poisson solve and E = -grad phi for box ``box``; returns (iterations,
+    relative residual)."""
+    it = C.c_int32()
+    res = C.c_double()
+    f = fields.c()
+    _check(lib().pic_es_solve(ctx, _species_array(species), len(species), box, C.byref(f),
+                              _ptr(phi), tol, max_iter, C.byref(it), C.byref(res)))
+    return int(it.value), float(res.value)
+
+
+def pic_es_push(ctx, fields: DeviceFields, species):
+    f = fields.c()
+    _check(lib().pic_es_push(ctx, C.byref(f), _species_array(species), len(species)))
+
+
+def pic_slice_moments(ctx, species, box: int, nz: int, out: torch.Tensor = None):
+    """(nsp, n_z, 5) FP64 on the device: per z layer sum w, w u_x, w u_y,
+    w u_z, w m (gamma - 1)."""
+    if out is None:
+        out = torch.empty((len(species), nz, 5), dtype=torch.float64, device="cuda")
+    _check(lib().pic_slice_moments(ctx, _species_array(species), len(species), box, _ptr(out)))
     return out
 
 

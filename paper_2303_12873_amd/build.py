@@ -36,6 +36,9 @@ COMMON = [
 UNITS = [
     ("libpic.hip", "libpic.o", []),
     ("pic_aux.hip", "pic_aux.o", []),
+    ("pic_slab.hip", "pic_slab.o", []),
+    ("pic_bound.hip", "pic_bound.o", []),
+    ("pic_es.hip", "pic_es.o", []),
 ] + [
     ("pic_particles.hip", f"pic_particles_o{o}_p{p}_t{t}.o",
      [f"-DPIC_ORDER={o}", f"-DPIC_PREC={p}", f"-DPIC_PART={t}"])

@@ -20,6 +20,7 @@
 
 using namespace pic;
 
+
 namespace {
 
 thread_local std::string g_last_error;
@@ -37,6 +38,7 @@ pic_status fail(pic_status s, const std::string &msg) {
     } while (0)
 
 constexpr int LDS_BYTES_MAX = 160 * 1024 - 256;   // leave room for static LDS
+constexpr int RANK_BITS = 4;                      // ranks of the rank-major order (0..15)
 
 int halo_gl(int o) { return o == 1 ? 1 : (o == 2 ? 1 : 2); }
 int halo_gh(int o) { return o == 1 ? 1 : 2; }
@@ -139,6 +141,29 @@ struct pic_ctx {
     int clock_khz = 0;
     bool capturing = false;
     hipStream_t cap_stream = nullptr;   // private stream graphs are recorded on
+    // partial sums of pic_energy
+    double *energy_part = nullptr;
+    size_t energy_cap = 0;
+    // z-slab particle migration: direction flags and their prefixes (6 x
+    // mig_cap ints), scan scratch, per-species totals (3 each) and per
+    // species staging / send arrays
+    int *mig_flags = nullptr;
+    long long mig_cap = 0;
+    int *mig_scan = nullptr;
+    size_t mig_scan_cap = 0;
+    int *mig_tot = nullptr;
+    int mig_tot_cap = 0;
+    struct MigStore {
+        MigBuffers b{};
+        long long cap[3] = {0, 0, 0};     // stay, down, up
+        int na = 0, esize = 0;
+    };
+    std::vector<MigStore> mig_store;
+    // electrostatic solve: rhs, r, p, Ap, ones (es_cap doubles each),
+    // per-block partial sums and scalars
+    double *es_vec = nullptr;
+    long long es_cap = 0;
+    double *es_part = nullptr, *es_sc = nullptr;
 };
 
 namespace {
@@ -233,6 +258,29 @@ pic_status validate_species(pic_ctx *c, const pic_species *sp, int nsp) {
     return PIC_OK;
 }
 
+// Arguments of the energy reductions: validated on the host without any
+// device call; species of other boxes get np = 0 (energy 0).
+pic_status energy_args(pic_ctx *c, const pic_fields *f, const pic_species *sp, int nsp, int box,
+                       const double *out, EnergySp *es) {
+    if (!c) return fail(PIC_ERR_ARG, "ctx is NULL");
+    if (box < 0 || box >= c->nboxes || !out) return fail(PIC_ERR_ARG, "bad box or out");
+    if (nsp > ENERGY_MAX_SPECIES)
+        return fail(PIC_ERR_ARG, "energy reductions take at most " +
+                                     std::to_string(ENERGY_MAX_SPECIES) + " species");
+    if (!f) return fail(PIC_ERR_ARG, "fields is NULL");
+    for (int d = 0; d < 3; ++d)
+        if (!f->E[d] || !f->B[d]) return fail(PIC_ERR_ARG, "E/B pointer is NULL");
+    pic_status st = validate_species(c, sp, nsp);
+    if (st != PIC_OK) return st;
+    for (int s = 0; s < nsp; ++s) {
+        es[s].np = sp[s].box == box ? sp[s].np : 0;
+        es[s].m = sp[s].m;
+        for (int d = 0; d < 3; ++d) es[s].u[d] = sp[s].u[d];
+        es[s].w = sp[s].w;
+    }
+    return PIC_OK;
+}
+
 // Upload the species table when the binding changed; (re)size per-species
 // scratch.  need_push_scratch: also allocate the x^n scratch.
 pic_status bind_species(pic_ctx *c, const pic_species *sp, int nsp, bool need_push_scratch) {
@@ -295,6 +343,8 @@ pic_status bind_species(pic_ctx *c, const pic_species *sp, int nsp, bool need_pu
         d.carry = sl.carry;
         d.strag = sl.strag;
         d.tile_off = sl.tile_off;
+        d.pusher = c->tun.pusher;
+        d.galerkin = c->tun.gather;
         d.spread = c->tun.quad_spread > 0 ||
                    (c->tun.quad_spread == 0 && p.np >= 6 * c->hbox[p.box].ncells);
         prefix[s + 1] = prefix[s] + b.ntiles;
@@ -366,6 +416,8 @@ KParams make_params(pic_ctx *c, const pic_fields *f, int nsp) {
     k.queue = c->queue;
     k.lds_field_bytes = (int)c->lds_field_bytes;
     k.lane_stride = c->tun.lane_stride;
+    // DPP quad pooling needs whole groups of four of one cell in a row
+    k.quad = c->tun.lane_stride <= 1 && c->tun.cell_order == 2;
     for (int d = 0; d < 3; ++d) k.margin[d] = c->margin[d];
     k.jrow = c->jrow;
     k.frow = c->frow;
@@ -477,7 +529,8 @@ pic_status ensure_sort_scratch(pic_ctx *c, long long np, long long nitems_cap) {
     size_t need_counts = (size_t)radix_blocks(np) * 256 + 256;
     size_t need_scan = std::max(scan_scratch_ints((long long)need_counts),
                                 scan_scratch_ints((long long)c->nbslots + 1));
-    if (c->tun.cell_order == 2) need_scan = std::max(need_scan, scan_scratch_ints(np));
+    if (c->tun.cell_order == 2 || c->tun.cell_order == 4)
+        need_scan = std::max(need_scan, scan_scratch_ints(np));
     if (c->counts_cap < need_counts) {
         if (c->capturing) return fail(PIC_ERR_STATE, "scratch growth during graph capture");
         (void)hipStreamSynchronize(c->stream);
@@ -541,7 +594,7 @@ pic_status do_sort(pic_ctx *c, const pic_species *sp, int nsp, int32_t *const *p
         // cell bits of the within-tile order (0: tile id only)
         // (cell_order 1/2 add two class bits; 3 orders by cell alone)
         int cb = 0;
-        const int classes = c->tun.cell_order == 3 ? 0 : 1;
+        const int classes = (c->tun.cell_order == 3 || c->tun.cell_order == 4) ? 0 : 1;
         if (c->tun.cell_order) {
             const int vol = b.tile[0] * (b.dim == 3 ? b.tile[1] : 1) * b.tile[2];
             cb = key_bits(vol);
@@ -558,7 +611,25 @@ pic_status do_sort(pic_ctx *c, const pic_species *sp, int nsp, int32_t *const *p
             cur = 1 - cur;
         }
         const int *perm = c->vals[cur];
-        HIP_TRY(launch_tile_offsets(c->keys[cur], np, nkeys, shift, sl.tile_off, S));
+        int kshift = shift;
+        if (cb && c->tun.cell_order == 4) {
+            // rank-major: (tile, rank in cell) keys, then stable passes over
+            // them (ties stay in cell order)
+            int *heads = (int *)c->tmp, *starts = heads + np;
+            HIP_TRY(rank_keys(c->keys[cur], np, cb, RANK_BITS, heads, starts, c->keys[1 - cur],
+                              c->sort_tot, c->scan_scr, S));
+            HIP_TRY(launch_copy4(c->vals[cur], c->vals[1 - cur], np, S));
+            cur = 1 - cur;
+            const int passes2 = (key_bits(nkeys) + RANK_BITS + 7) / 8;
+            for (int ps = 0; ps < passes2; ++ps) {
+                HIP_TRY(radix_pass(c->keys[cur], c->vals[cur], c->keys[1 - cur], c->vals[1 - cur], np,
+                                   8 * ps, c->counts, c->scan_scr, S));
+                cur = 1 - cur;
+            }
+            perm = c->vals[cur];
+            kshift = RANK_BITS;
+        }
+        HIP_TRY(launch_tile_offsets(c->keys[cur], np, nkeys, kshift, sl.tile_off, S));
         if (cb && c->tun.cell_order == 2) {
             HIP_TRY(quads_first(c->keys[cur], c->vals[cur], np, shift, sl.tile_off, c->keys[1 - cur],
                                 (int *)c->tmp, c->vals[1 - cur], c->sort_tot, c->scan_scr, S));
@@ -593,7 +664,7 @@ pic_status do_sort(pic_ctx *c, const pic_species *sp, int nsp, int32_t *const *p
             }
         }
         if (perm_out && perm_out[s]) HIP_TRY(launch_copy4(perm, perm_out[s], np, S));
-        if (key_out && key_out[s]) HIP_TRY(launch_shift_copy(c->keys[cur], key_out[s], np, shift, S));
+        if (key_out && key_out[s]) HIP_TRY(launch_shift_copy(c->keys[cur], key_out[s], np, kshift, S));
         if (off_out && off_out[s]) HIP_TRY(launch_copy4(sl.tile_off, off_out[s], b.ntiles + 1, S));
         sl.sorted = true;
     }
@@ -612,6 +683,398 @@ pic_status do_fdtd(pic_ctx *c, pic_fields *f) {
     KParams k = make_params(c, f, 0);
     HIP_TRY(launch_fdtd(c->prec == PIC_FP64 ? 0 : 1, k.f, c->dbox, c->dfp, c->nboxes,
                         c->total_cells, c->stream));
+    return PIC_OK;
+}
+
+// ---------------------------------------------------------------- z slabs
+
+pic_status slab_check(pic_ctx *c, int g) {
+    if (!c) return fail(PIC_ERR_ARG, "ctx is NULL");
+    if (g < 3) return fail(PIC_ERR_ARG, "slab guard must be >= 3 layers");
+    const DevBox &b0 = c->hbox[0];
+    for (int s = 0; s < c->nboxes; ++s) {
+        const DevBox &b = c->hbox[s];
+        if (b.dim != b0.dim || b.n[0] != b0.n[0] || b.n[1] != b0.n[1] || b.dt != b0.dt ||
+            b.dx[0] != b0.dx[0] || b.dx[1] != b0.dx[1] || b.dx[2] != b0.dx[2])
+            return fail(PIC_ERR_ARG, "slab boxes must share dim, nx, ny, dx and dt");
+        if (b.n[2] - 2 * g < 2 * g)
+            return fail(PIC_ERR_ARG, "slab " + std::to_string(s) + ": interior of " +
+                                         std::to_string(b.n[2] - 2 * g) + " layers < 2 x guard");
+    }
+    return PIC_OK;
+}
+
+// Arrays of one species as migration sees them (NULL arrays of 2D left out).
+MigSpecies mig_species(pic_ctx *c, const pic_species &p) {
+    MigSpecies m{};
+    m.np = p.np;
+    m.zi = -1;
+    auto add = [&](void *a) { if (a) m.a[m.na++] = a; };
+    if (c->prec == PIC_FP64) {
+        add(p.x[0]);
+        add(p.x[1]);
+        m.zi = m.na;
+        add(p.x[2]);
+    } else {
+        add(p.cell);
+        add(p.off[0]);
+        add(p.off[1]);
+        add(p.off[2]);
+    }
+    add(p.u[0]);
+    add(p.u[1]);
+    add(p.u[2]);
+    add(p.w);
+    return m;
+}
+
+pic_status mig_flags_and_scans(pic_ctx *c, const MigSpecies &m, int g, int nzs, int nxy, int *tot) {
+    const int prec = c->prec == PIC_FP64 ? 0 : 1;
+    const long long n = c->mig_cap;
+    int *st = c->mig_flags, *dn = st + n, *up = dn + n;
+    int *pst = up + n, *pdn = pst + n, *pup = pdn + n;
+    HIP_TRY(launch_mig_flags(prec, m, g, nzs, nxy, st, dn, up, c->stream));
+    HIP_TRY(scan_exclusive(st, pst, m.np, tot, c->mig_scan, c->stream));
+    HIP_TRY(scan_exclusive(dn, pdn, m.np, tot + 1, c->mig_scan, c->stream));
+    HIP_TRY(scan_exclusive(up, pup, m.np, tot + 2, c->mig_scan, c->stream));
+    return PIC_OK;
+}
+
+pic_status grow_buffer(void **p, long long &cap, long long need, size_t esize) {
+    if (cap >= need) return PIC_OK;
+    if (*p) (void)hipFree(*p);
+    *p = nullptr;
+    cap = 0;
+    if (hipMalloc(p, (size_t)std::max<long long>(need, 1) * esize) != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return fail(PIC_ERR_OOM, "migration buffer allocation failed");
+    }
+    cap = need;
+    return PIC_OK;
+}
+
+pic_status slab_migrate(pic_ctx *c, pic_species *sp, int nsp, int g, const int64_t *cap,
+                        int64_t *np_out) {
+    pic_status st = slab_check(c, g);
+    if (st != PIC_OK) return st;
+    if (c->capturing) return fail(PIC_ERR_STATE, "pic_slab_migrate cannot be captured");
+    const int nslab = c->nboxes;
+    if (nsp < 1 || nsp % nslab) return fail(PIC_ERR_ARG, "nsp must be a multiple of the slab count");
+    if (!cap || !np_out) return fail(PIC_ERR_ARG, "cap or np_out is NULL");
+    const int nkind = nsp / nslab;
+    for (int i = 0; i < nsp; ++i) {
+        if (sp[i].box != i / nkind) return fail(PIC_ERR_ARG, "species must be given slab-major (box == i / kinds)");
+        if (sp[i].np > cap[i]) return fail(PIC_ERR_ARG, "species count above its capacity");
+        if (cap[i] >= (1ll << 31)) return fail(PIC_ERR_ARG, "capacity out of range");
+    }
+    if ((st = validate_species(c, sp, nsp)) != PIC_OK) return st;
+    const int nxy = c->hbox[0].n[0] * c->hbox[0].n[1];
+    long long maxnp = 1;
+    for (int i = 0; i < nsp; ++i) maxnp = std::max(maxnp, (long long)sp[i].np);
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    if (c->mig_cap < maxnp) {
+        drop_graphs(c);
+        dfree(c->mig_flags);
+        c->mig_cap = 0;
+        if ((st = dalloc(&c->mig_flags, (size_t)maxnp * 6)) != PIC_OK) return st;
+        c->mig_cap = maxnp;
+    }
+    const size_t need_scan = scan_scratch_ints(maxnp);
+    if (c->mig_scan_cap < need_scan) {
+        dfree(c->mig_scan);
+        c->mig_scan_cap = 0;
+        if ((st = dalloc(&c->mig_scan, need_scan)) != PIC_OK) return st;
+        c->mig_scan_cap = need_scan;
+    }
+    if (c->mig_tot_cap < 3 * nsp) {
+        dfree(c->mig_tot);
+        c->mig_tot_cap = 0;
+        if ((st = dalloc(&c->mig_tot, (size_t)3 * nsp)) != PIC_OK) return st;
+        c->mig_tot_cap = 3 * nsp;
+    }
+    if ((int)c->mig_store.size() < nsp) c->mig_store.resize(nsp);
+    std::vector<MigSpecies> ms(nsp);
+    const size_t esize = c->prec == PIC_FP64 ? 8 : 4;
+    // counts of stayers and leavers of every species
+    for (int i = 0; i < nsp; ++i) {
+        ms[i] = mig_species(c, sp[i]);
+        const int nzs = c->hbox[sp[i].box].n[2] - 2 * g;
+        if ((st = mig_flags_and_scans(c, ms[i], g, nzs, nxy, c->mig_tot + 3 * i)) != PIC_OK) return st;
+    }
+    std::vector<int> tot(3 * nsp);
+    HIP_TRY(hipMemcpyAsync(tot.data(), c->mig_tot, tot.size() * sizeof(int), hipMemcpyDeviceToHost,
+                           c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    for (int i = 0; i < nsp; ++i)
+        if (sp[i].np == 0) tot[3 * i] = tot[3 * i + 1] = tot[3 * i + 2] = 0;
+    auto lower = [&](int i) { const int s = i / nkind; return ((s + nslab - 1) % nslab) * nkind + i % nkind; };
+    auto upper = [&](int i) { const int s = i / nkind; return ((s + 1) % nslab) * nkind + i % nkind; };
+    std::vector<long long> nnew(nsp);
+    for (int i = 0; i < nsp; ++i) {
+        nnew[i] = (long long)tot[3 * i] + tot[3 * lower(i) + 2] + tot[3 * upper(i) + 1];
+        if (nnew[i] > cap[i])
+            return fail(PIC_ERR_ARG, "species " + std::to_string(i) + ": " + std::to_string(nnew[i]) +
+                                         " particles after migration exceed its capacity");
+    }
+    // staging / send arrays
+    for (int i = 0; i < nsp; ++i) {
+        auto &S = c->mig_store[i];
+        if (S.na != ms[i].na || S.esize != (int)esize) {
+            for (int a = 0; a < MIG_ARRAYS; ++a) {
+                if (S.b.stay[a]) (void)hipFree(S.b.stay[a]);
+                if (S.b.down[a]) (void)hipFree(S.b.down[a]);
+                if (S.b.up[a]) (void)hipFree(S.b.up[a]);
+            }
+            S = pic_ctx::MigStore{};
+            S.na = ms[i].na;
+            S.esize = (int)esize;
+        }
+        for (int k = 0; k < 3; ++k) {
+            const long long need = tot[3 * i + k];
+            if (S.cap[k] >= need) continue;
+            for (int a = 0; a < S.na; ++a) {
+                void **bp = k == 0 ? &S.b.stay[a] : (k == 1 ? &S.b.down[a] : &S.b.up[a]);
+                long long cp = S.cap[k];
+                if ((st = grow_buffer(bp, cp, need, esize)) != PIC_OK) return st;
+            }
+            S.cap[k] = need;
+        }
+    }
+    // leavers out, stayers compacted
+    const int prec = c->prec == PIC_FP64 ? 0 : 1;
+    for (int i = 0; i < nsp; ++i) {
+        if (sp[i].np == 0) continue;
+        const int nzs = c->hbox[sp[i].box].n[2] - 2 * g;
+        const int nzp = c->hbox[sp[lower(i)].box].n[2] - 2 * g;
+        if ((st = mig_flags_and_scans(c, ms[i], g, nzs, nxy, c->mig_tot + 3 * i)) != PIC_OK) return st;
+        const long long n = c->mig_cap;
+        const int *fs = c->mig_flags;
+        HIP_TRY(launch_mig_scatter(prec, ms[i], fs, fs + n, fs + 2 * n, fs + 3 * n, fs + 4 * n,
+                                   fs + 5 * n, c->mig_store[i].b, nzp, nzs, nxy, c->stream));
+    }
+    // stayers, then arrivals from below and from above
+    for (int i = 0; i < nsp; ++i) {
+        MigSpecies m = ms[i];
+        m.np = nnew[i];
+        HIP_TRY(launch_mig_gather(prec, m, tot[3 * i], c->mig_store[i].b, tot[3 * lower(i) + 2],
+                                  c->mig_store[lower(i)].b, tot[3 * upper(i) + 1],
+                                  c->mig_store[upper(i)].b, c->stream));
+        np_out[i] = nnew[i];
+    }
+    return PIC_OK;
+}
+
+// ---------------------------------------------------------------- boundaries
+
+pic_status ensure_mig_scratch(pic_ctx *c, long long maxnp, int nsp) {
+    pic_status st;
+    if (c->mig_cap < maxnp) {
+        drop_graphs(c);
+        dfree(c->mig_flags);
+        c->mig_cap = 0;
+        if ((st = dalloc(&c->mig_flags, (size_t)maxnp * 6)) != PIC_OK) return st;
+        c->mig_cap = maxnp;
+    }
+    const size_t need_scan = scan_scratch_ints(maxnp);
+    if (c->mig_scan_cap < need_scan) {
+        dfree(c->mig_scan);
+        c->mig_scan_cap = 0;
+        if ((st = dalloc(&c->mig_scan, need_scan)) != PIC_OK) return st;
+        c->mig_scan_cap = need_scan;
+    }
+    if (c->mig_tot_cap < 3 * nsp) {
+        dfree(c->mig_tot);
+        c->mig_tot_cap = 0;
+        if ((st = dalloc(&c->mig_tot, (size_t)3 * nsp)) != PIC_OK) return st;
+        c->mig_tot_cap = 3 * nsp;
+    }
+    if ((int)c->mig_store.size() < nsp) c->mig_store.resize(nsp);
+    return PIC_OK;
+}
+
+pic_status ensure_mig_store(pic_ctx *c, int i, int na, size_t esize, int kind, long long need) {
+    auto &S = c->mig_store[i];
+    if (S.na != na || S.esize != (int)esize) {
+        for (int a = 0; a < MIG_ARRAYS; ++a) {
+            if (S.b.stay[a]) (void)hipFree(S.b.stay[a]);
+            if (S.b.down[a]) (void)hipFree(S.b.down[a]);
+            if (S.b.up[a]) (void)hipFree(S.b.up[a]);
+        }
+        S = pic_ctx::MigStore{};
+        S.na = na;
+        S.esize = (int)esize;
+    }
+    if (S.cap[kind] >= need) return PIC_OK;
+    for (int a = 0; a < S.na; ++a) {
+        void **bp = kind == 0 ? &S.b.stay[a] : (kind == 1 ? &S.b.down[a] : &S.b.up[a]);
+        long long cp = S.cap[kind];
+        pic_status st = grow_buffer(bp, cp, need, esize);
+        if (st != PIC_OK) return st;
+    }
+    S.cap[kind] = need;
+    return PIC_OK;
+}
+
+pic_status window_shift(pic_ctx *c, pic_fields *f, pic_species *sp, int nsp, int box,
+                        const pic_species *inj, const int64_t *cap, int64_t *np_out) {
+    if (!c) return fail(PIC_ERR_ARG, "ctx is NULL");
+    if (c->capturing) return fail(PIC_ERR_STATE, "pic_window_shift cannot be captured");
+    if (box < 0 || box >= c->nboxes) return fail(PIC_ERR_ARG, "bad box");
+    if (!cap || !np_out || (nsp > 0 && !inj)) return fail(PIC_ERR_ARG, "cap, np_out or inject is NULL");
+    pic_status st = check_fields(c, f, true);
+    if (st != PIC_OK) return st;
+    if ((st = validate_species(c, sp, nsp)) != PIC_OK) return st;
+    for (int i = 0; i < nsp; ++i) {
+        if (sp[i].box != box) continue;
+        if (inj[i].np < 0 || sp[i].np > cap[i] || cap[i] >= (1ll << 31))
+            return fail(PIC_ERR_ARG, "bad count or capacity (species " + std::to_string(i) + ")");
+        if (inj[i].np > 0) {
+            pic_species t = inj[i];
+            t.box = box;
+            if ((st = validate_species(c, &t, 1)) != PIC_OK) return st;
+        }
+    }
+    DevBox &hb = c->hbox[box];
+    const int nz = hb.n[2], nxy = hb.n[0] * hb.n[1];
+    const int k = ((hb.zoff % nz) + nz) % nz;       // array layer leaving the frame
+    const int prec = c->prec == PIC_FP64 ? 0 : 1;
+    long long maxnp = 1;
+    for (int i = 0; i < nsp; ++i) maxnp = std::max(maxnp, (long long)sp[i].np);
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    if ((st = ensure_mig_scratch(c, maxnp, std::max(nsp, 1))) != PIC_OK) return st;
+    void *comps[6] = {f->E[0], f->E[1], f->E[2], f->B[0], f->B[1], f->B[2]};
+    HIP_TRY(launch_zero_layer(prec, comps, c->dbox, box, nxy, k, c->stream));
+    hb.zoff = (k + 1) % nz;
+    HIP_TRY(launch_box_zoff(c->dbox, box, hb.zoff, c->stream));
+    std::vector<MigSpecies> ms(std::max(nsp, 1));
+    for (int i = 0; i < nsp; ++i) {
+        np_out[i] = sp[i].np;
+        if (sp[i].box != box) continue;
+        ms[i] = mig_species(c, sp[i]);
+        HIP_TRY(launch_win_flags(prec, ms[i], k, nxy, c->mig_flags, c->stream));
+        HIP_TRY(scan_exclusive(c->mig_flags, c->mig_flags + c->mig_cap, sp[i].np, c->mig_tot + 3 * i,
+                               c->mig_scan, c->stream));
+        if (sp[i].np == 0) continue;
+        // the compaction needs this species' flags and positions now
+        std::vector<int> one(1);
+        HIP_TRY(hipMemcpyAsync(one.data(), c->mig_tot + 3 * i, sizeof(int), hipMemcpyDeviceToHost,
+                               c->stream));
+        HIP_TRY(hipStreamSynchronize(c->stream));
+        const long long nstay = one[0];
+        const long long n = nstay + inj[i].np;
+        if (n > cap[i])
+            return fail(PIC_ERR_ARG, "species " + std::to_string(i) + ": " + std::to_string(n) +
+                                         " particles after the shift exceed its capacity");
+        const size_t esize = c->prec == PIC_FP64 ? 8 : 4;
+        if ((st = ensure_mig_store(c, i, ms[i].na, esize, 0, std::max(nstay, 1ll))) != PIC_OK) return st;
+        HIP_TRY(launch_win_compact(prec, ms[i], c->mig_flags, c->mig_flags + c->mig_cap,
+                                   c->mig_store[i].b, c->stream));
+        MigSpecies in = mig_species(c, inj[i]);
+        in.np = inj[i].np;
+        MigSpecies out = ms[i];
+        out.np = n;
+        HIP_TRY(launch_win_fill(prec, out, nstay, c->mig_store[i].b, in, hb.zoff, nz, nxy,
+                                c->stream));
+        np_out[i] = n;
+    }
+    // species with np == 0 before the shift: only the injected particles
+    for (int i = 0; i < nsp; ++i) {
+        if (sp[i].box != box || sp[i].np != 0 || inj[i].np == 0) continue;
+        if (inj[i].np > cap[i]) return fail(PIC_ERR_ARG, "injected particles exceed the capacity");
+        MigSpecies in = mig_species(c, inj[i]);
+        in.np = inj[i].np;
+        MigSpecies out = mig_species(c, sp[i]);
+        out.np = inj[i].np;
+        HIP_TRY(launch_win_fill(prec, out, 0, c->mig_store[0].b, in, hb.zoff, nz, nxy, c->stream));
+        np_out[i] = inj[i].np;
+    }
+    return PIC_OK;
+}
+
+// ---------------------------------------------------------------- electrostatic
+
+pic_status es_solve(pic_ctx *c, const pic_species *sp, int nsp, int box, pic_fields *f, double *phi,
+                    double tol, int max_iter, int32_t *iters_out, double *res_out) {
+    if (!c) return fail(PIC_ERR_ARG, "ctx is NULL");
+    if (c->capturing) return fail(PIC_ERR_STATE, "pic_es_solve cannot be captured");
+    if (box < 0 || box >= c->nboxes || !phi) return fail(PIC_ERR_ARG, "bad box or phi");
+    if (!(tol > 0.0) || max_iter < 1) return fail(PIC_ERR_ARG, "tol must be > 0 and max_iter >= 1");
+    pic_status st = check_fields(c, f, true);
+    if (st != PIC_OK) return st;
+    if ((st = bind_species(c, sp, nsp, false)) != PIC_OK) return st;
+    const long long n = c->hbox[box].ncells;
+    if (c->es_cap < n) {
+        HIP_TRY(hipStreamSynchronize(c->stream));
+        dfree(c->es_vec);
+        c->es_cap = 0;
+        if ((st = dalloc(&c->es_vec, (size_t)n * 5)) != PIC_OK) return st;
+        c->es_cap = n;
+        std::vector<double> one(n, 1.0);
+        HIP_TRY(hipMemcpy(c->es_vec + 4 * n, one.data(), n * sizeof(double), hipMemcpyHostToDevice));
+    }
+    if (!c->es_part) {
+        if ((st = dalloc(&c->es_part, (size_t)ES_DOT_GRID)) != PIC_OK) return st;
+        if ((st = dalloc(&c->es_sc, 8)) != PIC_OK) return st;
+    }
+    const long long cap = c->es_cap;
+    double *b = c->es_vec, *r = b + cap, *p = r + cap, *ap = p + cap, *ones = ap + cap;
+    double *part = c->es_part, *sc = c->es_sc;
+    hipStream_t S = c->stream;
+    // rhs: rho of the box's species, mean removed
+    HIP_TRY(launch_zero_d(b, n, S));
+    KParams k = make_params(c, f, nsp);
+    const int prec = c->prec == PIC_FP64 ? 0 : 1;
+    for (int s = 0; s < nsp; ++s) {
+        if (sp[s].box != box || sp[s].np == 0) continue;
+        HIP_TRY(k_rho_launch[c->order - 1][prec](k, s, sp[s].np, b, S));
+    }
+    HIP_TRY(launch_remove_mean(b, n, part, sc + 4, ones, S));
+    // conjugate gradients on -lap phi = b from phi = 0
+    HIP_TRY(launch_zero_d(phi, n, S));
+    HIP_TRY(launch_copy_d(b, r, n, S));
+    HIP_TRY(launch_copy_d(b, p, n, S));
+    HIP_TRY(launch_dot(r, r, n, part, sc, S));
+    double bb = 0.0;
+    HIP_TRY(hipMemcpyAsync(&bb, sc, sizeof(double), hipMemcpyDeviceToHost, S));
+    HIP_TRY(hipStreamSynchronize(S));
+    int it = 0;
+    double rr = bb;
+    if (bb > 0.0) {
+        while (it < max_iter) {
+            HIP_TRY(launch_neg_lap(c->dbox, box, n, p, ap, S));
+            HIP_TRY(launch_dot(p, ap, n, part, sc + 1, S));
+            HIP_TRY(launch_cg_xr(phi, r, p, ap, n, sc, S));
+            HIP_TRY(launch_dot(r, r, n, part, sc + 2, S));
+            HIP_TRY(launch_cg_p(p, r, n, sc, S));
+            HIP_TRY(launch_copy_scalar(sc, 0, 2, S));
+            ++it;
+            if (it % 16 == 0 || it == max_iter) {
+                HIP_TRY(hipMemcpyAsync(&rr, sc, sizeof(double), hipMemcpyDeviceToHost, S));
+                HIP_TRY(hipStreamSynchronize(S));
+                if (std::sqrt(rr / bb) <= tol) break;
+            }
+        }
+    }
+    HIP_TRY(launch_remove_mean(phi, n, part, sc + 4, ones, S));
+    HIP_TRY(launch_es_field(prec, c->dbox, box, n, phi, k.f, S));
+    if (iters_out) *iters_out = it;
+    if (res_out) *res_out = bb > 0.0 ? std::sqrt(rr / bb) : 0.0;
+    if (bb > 0.0 && std::sqrt(rr / bb) > tol)
+        return fail(PIC_ERR_STATE, "Poisson solve did not reach the tolerance in max_iter iterations");
+    return PIC_OK;
+}
+
+pic_status es_push(pic_ctx *c, const pic_fields *f, pic_species *sp, int nsp) {
+    if (!c) return fail(PIC_ERR_ARG, "ctx is NULL");
+    pic_status st = check_fields(c, f, true);
+    if (st != PIC_OK) return st;
+    if ((st = bind_species(c, sp, nsp, false)) != PIC_OK) return st;
+    for (int s = 0; s < nsp; ++s) c->slots[s].sorted = false;     // positions change
+    KParams k = make_params(c, f, nsp);
+    const int prec = c->prec == PIC_FP64 ? 0 : 1;
+    for (int s = 0; s < nsp; ++s)
+        HIP_TRY(launch_es_push(c->order, prec, c->dsp, s, sp[s].np, c->dbox, k.f, c->derr, c->stream));
     return PIC_OK;
 }
 
@@ -656,6 +1119,8 @@ pic_status pic_init(pic_ctx **out, const pic_box_desc *boxes, int32_t nboxes, pi
     t.cell_order = 0;
     t.quad_spread = 0;
     t.margin = 0;
+    t.pusher = 0;
+    t.gather = 0;
     if (tuning) {
         t.kernel = tuning->kernel;
         if (tuning->block) t.block = tuning->block;
@@ -666,6 +1131,8 @@ pic_status pic_init(pic_ctx **out, const pic_box_desc *boxes, int32_t nboxes, pi
         t.cell_order = tuning->cell_order;
         t.quad_spread = tuning->quad_spread;
         t.margin = tuning->margin;
+        t.pusher = tuning->pusher;
+        t.gather = tuning->gather;
     }
     if (t.kernel < 0 || t.kernel > 2) return fail(PIC_ERR_ARG, "bad kernel form");
     const int max_block = prec == PIC_FP64 ? 512 : 1024;
@@ -674,10 +1141,12 @@ pic_status pic_init(pic_ctx **out, const pic_box_desc *boxes, int32_t nboxes, pi
     if (t.chunk < 1) return fail(PIC_ERR_ARG, "chunk must be >= 1");
     if (t.wg_per_cu < 1 || t.wg_per_cu > 64) return fail(PIC_ERR_ARG, "wg_per_cu must be 1..64");
     if (t.lane_stride < 1 || t.lane_stride > 64) return fail(PIC_ERR_ARG, "lane_stride must be 1..64");
-    if (t.cell_order < -1 || t.cell_order > 3) return fail(PIC_ERR_ARG, "cell_order must be -1..3");
+    if (t.cell_order < -1 || t.cell_order > 4) return fail(PIC_ERR_ARG, "cell_order must be -1..4");
     if (t.pad < -1 || t.pad > 2) return fail(PIC_ERR_ARG, "pad must be -1..2");
     if (t.quad_spread < -1 || t.quad_spread > 1) return fail(PIC_ERR_ARG, "quad_spread must be -1..1");
     if (t.margin < -1 || t.margin > 0) return fail(PIC_ERR_ARG, "margin must be -1 or 0");
+    if (t.pusher < 0 || t.pusher > 1) return fail(PIC_ERR_ARG, "pusher must be 0 (Boris) or 1 (Vay)");
+    if (t.gather < 0 || t.gather > 1) return fail(PIC_ERR_ARG, "gather must be 0 or 1 (Galerkin)");
     t.cell_order = t.cell_order == 0 ? (t.kernel == PIC_KERNEL_BATCHED ? 2 : 0) : std::max(t.cell_order, 0);
 
     pic_ctx *c = new pic_ctx();
@@ -980,16 +1449,117 @@ pic_status pic_div_edge(pic_ctx *c, int32_t box, double *const v[3], double *out
 
 pic_status pic_energy(pic_ctx *c, const pic_fields *f, const pic_species *sp, int32_t nsp,
                       int32_t box, double *out) {
+    EnergySp es[ENERGY_MAX_SPECIES];
+    pic_status st = energy_args(c, f, sp, nsp, box, out, es);
+    if (st != PIC_OK) return st;
+    const size_t need = energy_scratch_doubles(nsp);
+    if (c->energy_cap < need) {
+        if (c->capturing) return fail(PIC_ERR_STATE, "scratch growth during graph capture");
+        HIP_TRY(hipStreamSynchronize(c->stream));
+        dfree(c->energy_part);
+        if ((st = dalloc(&c->energy_part, need)) != PIC_OK) return st;
+        c->energy_cap = need;
+    }
+    KParams k = make_params(c, f, 0);
+    HIP_TRY(launch_energy(c->prec == PIC_FP64 ? 0 : 1, k.f, c->dbox, box, c->hbox[box].ncells, es,
+                          nsp, c->energy_part, out, c->stream));
+    return PIC_OK;
+}
+
+pic_status pic_slab_fill_guards(pic_ctx *c, pic_fields *f, int32_t guard) {
+    pic_status st = slab_check(c, guard);
+    if (st != PIC_OK) return st;
+    if ((st = check_fields(c, f, true)) != PIC_OK) return st;
+    void *comps[6] = {f->E[0], f->E[1], f->E[2], f->B[0], f->B[1], f->B[2]};
+    const long long nxy = (long long)c->hbox[0].n[0] * c->hbox[0].n[1];
+    HIP_TRY(launch_slab_fill(c->prec == PIC_FP64 ? 0 : 1, comps, 6, c->dbox, c->nboxes, guard, nxy,
+                             c->stream));
+    return PIC_OK;
+}
+
+pic_status pic_slab_reduce_j(pic_ctx *c, pic_fields *f, int32_t guard) {
+    pic_status st = slab_check(c, guard);
+    if (st != PIC_OK) return st;
+    if ((st = check_fields(c, f, false)) != PIC_OK) return st;
+    const long long nxy = (long long)c->hbox[0].n[0] * c->hbox[0].n[1];
+    HIP_TRY(launch_slab_sum_j(f->J, c->dbox, c->nboxes, guard, nxy, c->stream));
+    void *comps[3] = {f->J[0], f->J[1], f->J[2]};
+    HIP_TRY(launch_slab_fill(0, comps, 3, c->dbox, c->nboxes, guard, nxy, c->stream));
+    return PIC_OK;
+}
+
+pic_status pic_slab_migrate(pic_ctx *c, pic_species *sp, int32_t nsp, int32_t guard,
+                            const int64_t *cap, int64_t *np_out) {
+    return slab_migrate(c, sp, nsp, guard, cap, np_out);
+}
+
+pic_status pic_set_absorber(pic_ctx *c, int32_t box, int32_t cells, double sigma_max,
+                            int32_t power) {
+    if (!c) return fail(PIC_ERR_ARG, "ctx is NULL");
+    if (box < 0 || box >= c->nboxes) return fail(PIC_ERR_ARG, "bad box");
+    DevBox &b = c->hbox[box];
+    if (cells < 0 || 2 * cells > b.n[2]) return fail(PIC_ERR_ARG, "absorber cells must be 0..n_z/2");
+    if (!(sigma_max >= 0.0) || !std::isfinite(sigma_max)) return fail(PIC_ERR_ARG, "bad sigma_max");
+    if (power < 0 || power > 8) return fail(PIC_ERR_ARG, "absorber power must be 0..8");
+    if (c->capturing) return fail(PIC_ERR_STATE, "pic_set_absorber cannot be captured");
+    b.abs_cells = cells;
+    b.abs_sigma = sigma_max;
+    b.abs_power = power;
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    HIP_TRY(hipMemcpy(c->dbox + box, &b, sizeof(DevBox), hipMemcpyHostToDevice));
+    return PIC_OK;
+}
+
+pic_status pic_antenna_add(pic_ctx *c, pic_fields *f, int32_t box, const pic_antenna *an, double t) {
+    if (!c) return fail(PIC_ERR_ARG, "ctx is NULL");
+    if (box < 0 || box >= c->nboxes || !an) return fail(PIC_ERR_ARG, "bad box or antenna");
+    pic_status st = check_fields(c, f, false);
+    if (st != PIC_OK) return st;
+    const DevBox &b = c->hbox[box];
+    if (an->k < 0 || an->k >= b.n[2]) return fail(PIC_ERR_ARG, "antenna layer outside the box");
+    if (!(an->tau > 0.0) || !(an->waist > 0.0)) return fail(PIC_ERR_ARG, "antenna tau and waist must be > 0");
+    AntennaArgs a;
+    a.k = an->k; a.E0 = an->E0; a.omega = an->omega; a.waist = an->waist;
+    a.x0 = an->x0; a.y0 = an->y0; a.t0 = an->t0; a.tau = an->tau;
+    HIP_TRY(launch_antenna(f->J[0], c->dbox, box, (long long)b.n[0] * b.n[1], a, t, c->stream));
+    return PIC_OK;
+}
+
+pic_status pic_window_shift(pic_ctx *c, pic_fields *f, pic_species *sp, int32_t nsp, int32_t box,
+                            const pic_species *inject, const int64_t *cap, int64_t *np_out) {
+    return window_shift(c, f, sp, nsp, box, inject, cap, np_out);
+}
+
+pic_status pic_window_offset(pic_ctx *c, int32_t box, int32_t *zoff) {
+    if (!c || !zoff) return fail(PIC_ERR_ARG, "ctx or zoff is NULL");
+    if (box < 0 || box >= c->nboxes) return fail(PIC_ERR_ARG, "bad box");
+    *zoff = c->hbox[box].zoff;
+    return PIC_OK;
+}
+
+pic_status pic_es_solve(pic_ctx *c, const pic_species *sp, int32_t nsp, int32_t box, pic_fields *f,
+                        double *phi, double tol, int32_t max_iter, int32_t *iters_out,
+                        double *res_out) {
+    return es_solve(c, sp, nsp, box, f, phi, tol, max_iter, iters_out, res_out);
+}
+
+pic_status pic_es_push(pic_ctx *c, const pic_fields *f, pic_species *sp, int32_t nsp) {
+    return es_push(c, f, sp, nsp);
+}
+
+pic_status pic_slice_moments(pic_ctx *c, const pic_species *sp, int32_t nsp, int32_t box,
+                             double *out) {
     if (!c) return fail(PIC_ERR_ARG, "ctx is NULL");
     if (box < 0 || box >= c->nboxes || !out) return fail(PIC_ERR_ARG, "bad box or out");
-    pic_status st = check_fields(c, f, true);
+    pic_status st = bind_species(c, sp, nsp, false);
     if (st != PIC_OK) return st;
-    if ((st = bind_species(c, sp, nsp, false)) != PIC_OK) return st;
-    std::vector<long long> np(std::max(nsp, 1), 0);
-    for (int s = 0; s < nsp; ++s) np[s] = sp[s].box == box ? sp[s].np : 0;
-    KParams k = make_params(c, f, nsp);
-    HIP_TRY(launch_energy(c->prec == PIC_FP64 ? 0 : 1, k.f, c->dbox, box, c->hbox[box].ncells,
-                          c->dsp, np.data(), nsp, out, c->cus, c->stream));
+    const long long nz = c->hbox[box].n[2];
+    HIP_TRY(launch_zero_doubles(out, 5 * nz * nsp, c->stream));
+    const int prec = c->prec == PIC_FP64 ? 0 : 1;
+    for (int s = 0; s < nsp; ++s) {
+        if (sp[s].box != box) continue;
+        HIP_TRY(launch_slice_moments(prec, c->dsp, s, sp[s].np, c->dbox, out + 5 * nz * s, c->stream));
+    }
     return PIC_OK;
 }
 
@@ -1011,6 +1581,19 @@ pic_status pic_free(pic_ctx *c) {
     (void)hipStreamSynchronize(c->stream);
     drop_graphs(c);
     dfree(c->stamps);
+    dfree(c->energy_part);
+    dfree(c->mig_flags);
+    dfree(c->mig_scan);
+    dfree(c->mig_tot);
+    dfree(c->es_vec);
+    dfree(c->es_part);
+    dfree(c->es_sc);
+    for (auto &ms : c->mig_store)
+        for (int a = 0; a < MIG_ARRAYS; ++a) {
+            if (ms.b.stay[a]) (void)hipFree(ms.b.stay[a]);
+            if (ms.b.down[a]) (void)hipFree(ms.b.down[a]);
+            if (ms.b.up[a]) (void)hipFree(ms.b.up[a]);
+        }
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     for (auto &sl : c->slots) {
         for (int d = 0; d < 3; ++d) { dfree(sl.xo[d]); dfree(sl.offo[d]); }

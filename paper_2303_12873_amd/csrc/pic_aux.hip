@@ -177,6 +177,19 @@ __global__ void k_run_starts(const int *key, long long n, const int *heads_excl,
     if (i < n && run_head(key, i)) starts[heads_excl[i]] = (int)i;
 }
 
+// Keys of the rank-major order: the tile of a sorted (tile, cell) key and
+// the particle's rank within its run of equal keys (its cell), capped at
+// 2^rbits - 1: key2 = tile << rbits | rank.
+__global__ void k_rank_keys(const int *key, long long n, const int *heads_excl, const int *starts,
+                            int cbits, int rbits, int *key2) {
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int r = heads_excl[i] + run_head(key, i) - 1;
+    const int rmax = (1 << rbits) - 1;
+    const int rank = (int)min(i - (long long)starts[r], (long long)rmax);
+    key2[i] = ((key[i] >> cbits) << rbits) | rank;
+}
+
 __global__ void k_quad_flags(const int *key, long long n, const int *heads_excl, const int *starts,
                              const int *nruns, int *flag) {
     long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -386,7 +399,37 @@ __device__ inline CellNbr neighbours(const DevBox &b, long long local) {
                    id(im, j, k), id(i, jm, k), id(i, j, km)};
 }
 
-// B -= h curl E, curl E at the B points (Yee).  2D: no d/dy terms.
+// Conductivity of the absorbing layers at array height za (cell units) of
+// box b: frame height (za - zoff) mod n_z, depth d into a layer of L cells,
+// sigma_max (d / L)^p.
+__device__ inline double absorb_sigma(const DevBox &b, double za) {
+    const double nz = (double)b.n[2], L = (double)b.abs_cells;
+    double z = za - (double)b.zoff;
+    z -= nz * floor(z / nz);
+    double d = 0.0;
+    if (z < L) d = L - z;
+    else if (z > nz - L) d = z - (nz - L);
+    if (d <= 0.0) return 0.0;
+    double r = d / L, p = r;
+    for (int k = 1; k < b.abs_power; ++k) p *= r;
+    return b.abs_sigma * (b.abs_power == 0 ? 1.0 : p);
+}
+
+// Decay factor and source weight of a sub-step tau: exp(-sigma tau) and
+// (1 - exp(-sigma tau)) / sigma (tau when sigma = 0).
+__device__ inline void absorb_coef(double sigma, double tau, double &al, double &be) {
+    if (sigma == 0.0) { al = 1.0; be = tau; return; }
+    al = exp(-sigma * tau);
+    be = (1.0 - al) / sigma;
+}
+
+__device__ inline int cell_k(const DevBox &b, long long local) {
+    return (int)(local / ((long long)b.n[0] * b.n[1]));
+}
+
+// B -= h curl E, curl E at the B points (Yee).  2D: no d/dy terms.  In the
+// absorbing layers B <- exp(-sigma h) B - (1 - exp(-sigma h)) / sigma curl E,
+// sigma at each component's own z (B_x, B_y at k + 1/2, B_z at k).
 template <typename T>
 __global__ void k_faraday(DevFields f, const DevBox *boxes, const long long *fp, int nb,
                           long long total, double hfrac) {
@@ -405,6 +448,17 @@ __global__ void k_faraday(DevFields f, const DevBox *boxes, const long long *fp,
     T cx = dEz_dy - (Ey[q.zp] - ey) * iz;
     T cy = (Ex[q.zp] - ex) * iz - (Ez[q.xp] - ez) * ix;
     T cz = (Ey[q.xp] - ey) * ix - dEx_dy;
+    if (b.abs_cells > 0) {
+        const int k = cell_k(b, g - fp[bi]);
+        const double hh = hfrac * b.dt;
+        double a1, b1, a0, b0;
+        absorb_coef(absorb_sigma(b, k + 0.5), hh, a1, b1);
+        absorb_coef(absorb_sigma(b, (double)k), hh, a0, b0);
+        Bx[q.c] = (T)a1 * Bx[q.c] - (T)b1 * cx;
+        By[q.c] = (T)a1 * By[q.c] - (T)b1 * cy;
+        Bz[q.c] = (T)a0 * Bz[q.c] - (T)b0 * cz;
+        return;
+    }
     Bx[q.c] -= h * cx;
     By[q.c] -= h * cy;
     Bz[q.c] -= h * cz;
@@ -429,6 +483,17 @@ __global__ void k_ampere(DevFields f, const DevBox *boxes, const long long *fp, 
     T cx = dBz_dy - (by - By[q.zm]) * iz;
     T cy = (bx - Bx[q.zm]) * iz - (bz - Bz[q.xm]) * ix;
     T cz = (by - By[q.xm]) * ix - dBx_dy;
+    if (b.abs_cells > 0) {
+        // E_x, E_y at k, E_z at k + 1/2
+        const int k = cell_k(b, g - fp[bi]);
+        double a0, b0, a1, b1;
+        absorb_coef(absorb_sigma(b, (double)k), b.dt, a0, b0);
+        absorb_coef(absorb_sigma(b, k + 0.5), b.dt, a1, b1);
+        Ex[q.c] = (T)a0 * Ex[q.c] + (T)b0 * (cx - (T)f.J[0][q.c]);
+        Ey[q.c] = (T)a0 * Ey[q.c] + (T)b0 * (cy - (T)f.J[1][q.c]);
+        Ez[q.c] = (T)a1 * Ez[q.c] + (T)b1 * (cz - (T)f.J[2][q.c]);
+        return;
+    }
     Ex[q.c] += dt * (cx - (T)f.J[0][q.c]);
     Ey[q.c] += dt * (cy - (T)f.J[1][q.c]);
     Ez[q.c] += dt * (cz - (T)f.J[2][q.c]);
@@ -448,9 +513,13 @@ __global__ void k_div_edge(const DevBox *boxes, int bi, const double *vx, const 
 }
 
 // ------------------------------------------------------------ energies
+//
+// Two passes, deterministic: every block of the field and kinetic passes
+// writes its partial sums into its own slot of a scratch array (no atomics),
+// then one block adds each output's partials in slot order.
 
-// Sum of v over a 256-thread block (4 waves: DPP-free shuffle reduction in
-// each wave, then the four wave sums through LDS); the result is valid in
+// Sum of v over a 256-thread block (4 waves: shuffle reduction in each
+// wave, then the four wave sums through LDS); the result is valid in
 // thread 0.
 __device__ inline double block_sum256(double v, double *lds4) {
 #pragma unroll
@@ -463,11 +532,12 @@ __device__ inline double block_sum256(double v, double *lds4) {
     return t;
 }
 
-// Field energy of box bi: out[0] += 1/2 sum E.E dV, out[1] += 1/2 sum B.B dV
-// (FP64 sums; E, B in the context's precision).
+// Field energy partials of box bi: part[2 b] = 1/2 sum E.E dV and
+// part[2 b + 1] = 1/2 sum B.B dV over block b's cells (FP64 sums; E, B in
+// the context's precision).
 template <typename T>
 __global__ void __launch_bounds__(256) k_field_energy(DevFields f, const DevBox *boxes, int bi,
-                                                       double *out) {
+                                                       double *part) {
     __shared__ double red[4];
     const DevBox &b = boxes[bi];
     double se = 0.0, sb = 0.0;
@@ -486,17 +556,17 @@ __global__ void __launch_bounds__(256) k_field_energy(DevFields f, const DevBox 
     se = block_sum256(se, red);
     sb = block_sum256(sb, red);
     if (threadIdx.x == 0) {
-        atomicAdd(&out[0], se * hdv);
-        atomicAdd(&out[1], sb * hdv);
+        part[2 * blockIdx.x] = se * hdv;
+        part[2 * blockIdx.x + 1] = sb * hdv;
     }
 }
 
-// Kinetic energy of one species: *out += sum w m (gamma - 1), with
-// gamma - 1 = u.u / (1 + gamma) (no cancellation at small |u|).
+// Kinetic energy partials of one species: part[b] = sum over block b's
+// particles of w m (gamma - 1), gamma - 1 = u.u / (1 + gamma) (no
+// cancellation at small |u|).
 template <typename T>
-__global__ void __launch_bounds__(256) k_kinetic_energy(const DevSpecies *spt, int s, double *out) {
+__global__ void __launch_bounds__(256) k_kinetic_energy(EnergySp sp, double *part) {
     __shared__ double red[4];
-    const DevSpecies &sp = spt[s];
     const T *u0 = (const T *)sp.u[0], *u1 = (const T *)sp.u[1], *u2 = (const T *)sp.u[2];
     const T *w = (const T *)sp.w;
     double acc = 0.0;
@@ -507,11 +577,54 @@ __global__ void __launch_bounds__(256) k_kinetic_energy(const DevSpecies *spt, i
         acc += (double)w[i] * (uu / (1.0 + sqrt(1.0 + uu)));
     }
     acc = block_sum256(acc, red);
-    if (threadIdx.x == 0) atomicAdd(out, acc * sp.m);
+    if (threadIdx.x == 0) part[blockIdx.x] = acc * sp.m;
 }
 
-__global__ void k_zero_doubles(double *p, int n) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+// out[k] = sum of partials [off[k], off[k] + cnt[k]) with stride str[k]
+// (field parts interleave E and B), in slot order.  One block of 64 lanes.
+__global__ void k_energy_final(const double *part, EnergyPlan plan, double *out) {
+    const int k = blockIdx.x;
+    if (k >= plan.nout) return;
+    double acc = 0.0;
+    if (threadIdx.x == 0) {
+        for (int i = 0; i < plan.cnt[k]; ++i) acc += part[plan.off[k] + (long long)i * plan.str[k]];
+        out[k] = acc;
+    }
+}
+
+// Per-layer moments along z (window frame) of one species: out[5 k + q] +=
+// w, w u_x, w u_y, w u_z, w m (gamma - 1) of every particle in frame layer
+// k (FP64 atomics; summation order unspecified).
+template <int PREC>
+__global__ void k_slice_moments(const DevSpecies *spt, int s, const DevBox *boxes, double *out) {
+    const DevSpecies &sp = spt[s];
+    const DevBox &b = boxes[sp.box];
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= sp.np) return;
+    int k;
+    double u0, u1, u2, w;
+    if (PREC == 0) {
+        k = (int)floor(sp.x[2][i]);
+        u0 = ((const double *)sp.u[0])[i]; u1 = ((const double *)sp.u[1])[i];
+        u2 = ((const double *)sp.u[2])[i]; w = ((const double *)sp.w)[i];
+    } else {
+        k = sp.cell[i] / (b.n[0] * b.n[1]);
+        u0 = ((const float *)sp.u[0])[i]; u1 = ((const float *)sp.u[1])[i];
+        u2 = ((const float *)sp.u[2])[i]; w = ((const float *)sp.w)[i];
+    }
+    const int nz = b.n[2];
+    k = ((k - b.zoff) % nz + nz) % nz;
+    const double uu = u0 * u0 + u1 * u1 + u2 * u2;
+    double *o = out + 5LL * k;
+    atomicAdd(o + 0, w);
+    atomicAdd(o + 1, w * u0);
+    atomicAdd(o + 2, w * u1);
+    atomicAdd(o + 3, w * u2);
+    atomicAdd(o + 4, w * sp.m * (uu / (1.0 + sqrt(1.0 + uu))));
+}
+
+__global__ void k_zero_doubles(double *p, long long n) {
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0.0;
 }
 
@@ -617,6 +730,19 @@ hipError_t quads_first(const int *key, const int *perm_in, long long n, int shif
     return hipGetLastError();
 }
 
+hipError_t rank_keys(const int *key, long long n, int cbits, int rbits, int *heads, int *starts,
+                     int *key2, int *total, int *scan_scratch, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    const unsigned nb = blocks_for(n, 256);
+    hipLaunchKernelGGL(k_run_heads, dim3(nb), dim3(256), 0, st, key, n, heads);
+    hipError_t e = scan_exclusive(heads, heads, n, total, scan_scratch, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_run_starts, dim3(nb), dim3(256), 0, st, key, n, (const int *)heads, starts);
+    hipLaunchKernelGGL(k_rank_keys, dim3(nb), dim3(256), 0, st, key, n, (const int *)heads,
+                       (const int *)starts, cbits, rbits, key2);
+    return hipGetLastError();
+}
+
 hipError_t launch_shift_copy(const int *src, int *dst, long long n, int shift, hipStream_t st) {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_shift_copy, dim3(blocks_for(n, 256)), dim3(256), 0, st, src, dst, n, shift);
@@ -704,23 +830,55 @@ hipError_t launch_fdtd(int prec, const DevFields &f, const DevBox *boxes, const 
     return hipGetLastError();
 }
 
+size_t energy_scratch_doubles(int nsp) {
+    return (size_t)(2 + nsp) * ENERGY_MAX_GRID;
+}
+
 hipError_t launch_energy(int prec, const DevFields &f, const DevBox *boxes, int bi,
-                         long long ncells, const DevSpecies *spt, const long long *np, int nsp,
-                         double *out, int cus, hipStream_t st) {
-    hipLaunchKernelGGL(k_zero_doubles, dim3(blocks_for(2 + nsp, 256)), dim3(256), 0, st, out,
-                       2 + nsp);
-    const unsigned cap = (unsigned)(cus > 0 ? 4 * cus : 1024);
-    if (ncells > 0) {
-        const unsigned g = std::min(blocks_for(ncells, 256), cap);
-        if (prec == 0) hipLaunchKernelGGL(k_field_energy<double>, dim3(g), dim3(256), 0, st, f, boxes, bi, out);
-        else hipLaunchKernelGGL(k_field_energy<float>, dim3(g), dim3(256), 0, st, f, boxes, bi, out);
+                         long long ncells, const EnergySp *sps, int nsp, double *part,
+                         double *out, hipStream_t st) {
+    if (nsp < 0 || nsp > ENERGY_MAX_SPECIES) return hipErrorInvalidValue;
+    EnergyPlan plan;
+    plan.nout = 2 + nsp;
+    // field partials: slots [0, 2 gf), E and B interleaved
+    const unsigned gf = ncells > 0 ? std::min(blocks_for(ncells, 256), (unsigned)ENERGY_MAX_GRID) : 0;
+    plan.off[0] = 0; plan.cnt[0] = (int)gf; plan.str[0] = 2;
+    plan.off[1] = 1; plan.cnt[1] = (int)gf; plan.str[1] = 2;
+    if (gf > 0) {
+        if (prec == 0) hipLaunchKernelGGL(k_field_energy<double>, dim3(gf), dim3(256), 0, st, f, boxes, bi, part);
+        else hipLaunchKernelGGL(k_field_energy<float>, dim3(gf), dim3(256), 0, st, f, boxes, bi, part);
     }
+    // species s: slots [(2 + s) G, (2 + s) G + gs)
     for (int s = 0; s < nsp; ++s) {
-        if (np[s] <= 0) continue;
-        const unsigned g = std::min(blocks_for(np[s], 256), cap);
-        if (prec == 0) hipLaunchKernelGGL(k_kinetic_energy<double>, dim3(g), dim3(256), 0, st, spt, s, out + 2 + s);
-        else hipLaunchKernelGGL(k_kinetic_energy<float>, dim3(g), dim3(256), 0, st, spt, s, out + 2 + s);
+        const long long np = sps[s].np;
+        const unsigned gs = np > 0 ? std::min(blocks_for(np, 256), (unsigned)ENERGY_MAX_GRID) : 0;
+        plan.off[2 + s] = (2 + s) * ENERGY_MAX_GRID;
+        plan.cnt[2 + s] = (int)gs;
+        plan.str[2 + s] = 1;
+        if (gs == 0) continue;
+        double *p = part + (size_t)(2 + s) * ENERGY_MAX_GRID;
+        if (prec == 0) hipLaunchKernelGGL(k_kinetic_energy<double>, dim3(gs), dim3(256), 0, st, sps[s], p);
+        else hipLaunchKernelGGL(k_kinetic_energy<float>, dim3(gs), dim3(256), 0, st, sps[s], p);
     }
+    hipLaunchKernelGGL(k_energy_final, dim3(plan.nout), dim3(64), 0, st, (const double *)part, plan, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_slice_moments(int prec, const DevSpecies *spt, int s, long long np,
+                                const DevBox *boxes, double *out, hipStream_t st) {
+    if (np == 0) return hipSuccess;
+    if (prec == 0)
+        hipLaunchKernelGGL(k_slice_moments<0>, dim3(blocks_for(np, 256)), dim3(256), 0, st, spt, s,
+                           boxes, out);
+    else
+        hipLaunchKernelGGL(k_slice_moments<1>, dim3(blocks_for(np, 256)), dim3(256), 0, st, spt, s,
+                           boxes, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_doubles(double *p, long long n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero_doubles, dim3(blocks_for(n, 256)), dim3(256), 0, st, p, n);
     return hipGetLastError();
 }
 

@@ -22,6 +22,13 @@ struct DevBox {
     double dt;
     double dx[3];
     double inv_nx, inv_nxy;   // 1/n[0], 1/(n[0] n[1]) for index decoding
+    // absorbing layers of abs_cells cells at both z ends of the window
+    // frame, conductivity abs_sigma (d / abs_cells)^abs_power at depth d
+    // (abs_cells == 0: none); zoff: array layer of the window frame's
+    // layer 0 (a moving window advances it; the arrays are circular in z)
+    int abs_cells, abs_power;
+    double abs_sigma;
+    int zoff;
 };
 
 struct DevSpecies {
@@ -43,6 +50,8 @@ struct DevSpecies {
     // exclusive per-tile offsets from the last sort, ntiles+2 entries
     // (the extra bucket holds particles with invalid positions)
     int *tile_off;
+    int pusher;         // 0 Boris, 1 Vay
+    int galerkin;       // 1: Galerkin gather (order - 1 along staggered axes)
     int spread;         // tiled kernels at lane stride 1: a wave's 16 quads
                         // are taken ceil(nquads/16) quads apart, not in a
                         // row (several quads per cell)
@@ -78,6 +87,7 @@ struct KParams {
     int *queue;
     int lds_field_bytes;      // offset of the J region in dynamic LDS
     int lane_stride;          // lane -> particle stride inside a work item
+    int quad;                 // 1: fused kernels pool the deposit of aligned quads
     int margin[3];            // cells staged around each tile per axis (0 or 1)
     int jrow;                 // minimum row length of the LDS current tile
     int frow;                 // minimum row length of the LDS field tile

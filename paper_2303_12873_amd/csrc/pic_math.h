@@ -23,6 +23,15 @@ namespace pic {
 //                     P2 = P1(1-f),    P3 = f^3/6
 template <int O> struct Spline;
 
+// Order 0 (the nearest node; the Galerkin gather of order-1 shapes along a
+// staggered axis): reference cell of xi + 1/2, one node.
+template <> struct Spline<0> {
+    static constexpr int MLO = 0;
+    static constexpr bool EVEN = true;
+    template <typename R> __device__ static inline R P(int, R) { return R(1); }
+    template <typename R> __device__ static inline R D(int, R, R) { return R(0); }
+};
+
 template <> struct Spline<1> {
     static constexpr int MLO = 0;
     static constexpr bool EVEN = false;
@@ -98,6 +107,23 @@ __device__ inline GWin<O, R> gather_window(int c, R f, int st) {
     g.base = cc + S::MLO;
 #pragma unroll
     for (int m = 0; m <= O; ++m) g.w[m] = S::template P<R>(m, ff);
+    return g;
+}
+
+// Galerkin form along a staggered axis: the order-(O-1) window of the
+// half-shifted nodes, placed in the O+1 slots of the order-O window (its
+// nodes are a subset of them; the unused slot gets weight 0).
+template <int O, typename R>
+__device__ inline GWin<O, R> gather_window_galerkin(int c, R f) {
+    GWin<O, R> g = gather_window<O, R>(c, f, 1);
+    GWin<O - 1, R> l = gather_window<O - 1, R>(c, f, 1);
+    const int sh = l.base - g.base;          // 0 or 1
+#pragma unroll
+    for (int m = 0; m <= O; ++m) {
+        const R a = (m < O) ? l.w[m] : R(0);
+        const R b = (m >= 1) ? l.w[m - 1] : R(0);
+        g.w[m] = sh == 0 ? a : b;
+    }
     return g;
 }
 
@@ -204,6 +230,39 @@ __device__ inline void boris(R h, const R E[3], const R B[3], R u[3]) {
     u[0] = um0 + (up1 * s2 - up2 * s1) + h * E[0];
     u[1] = um1 + (up2 * s0 - up0 * s2) + h * E[1];
     u[2] = um2 + (up0 * s1 - up1 * s0) + h * E[2];
+}
+
+// Relativistic pusher of Vay (Phys. Plasmas 15, 056701, 2008), with h =
+// q dt / (2 m): u' = u + 2h (E + v x B / 2), tau = h B, then gamma^(n+1/2)
+// from sigma = gamma'^2 - tau^2 and u* = u'.tau, t = tau / gamma^(n+1/2),
+// u = (u' + (u'.t) t + u' x t) / (1 + t^2).  E + v x B vanishes exactly at
+// the E x B drift velocity.
+template <typename R>
+__device__ inline void vay(R h, const R E[3], const R B[3], R u[3]) {
+    const R gi0 = R(1) / sqrt(R(1) + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+    const R v0 = u[0] * gi0, v1 = u[1] * gi0, v2 = u[2] * gi0;
+    const R q2 = R(2) * h;
+    const R up0 = u[0] + q2 * (E[0] + R(0.5) * (v1 * B[2] - v2 * B[1]));
+    const R up1 = u[1] + q2 * (E[1] + R(0.5) * (v2 * B[0] - v0 * B[2]));
+    const R up2 = u[2] + q2 * (E[2] + R(0.5) * (v0 * B[1] - v1 * B[0]));
+    const R ta0 = h * B[0], ta1 = h * B[1], ta2 = h * B[2];
+    const R tau2 = ta0 * ta0 + ta1 * ta1 + ta2 * ta2;
+    const R us = up0 * ta0 + up1 * ta1 + up2 * ta2;
+    const R sig = (R(1) + up0 * up0 + up1 * up1 + up2 * up2) - tau2;
+    const R g1 = sqrt(R(0.5) * (sig + sqrt(sig * sig + R(4) * (tau2 + us * us))));
+    const R t0 = ta0 / g1, t1 = ta1 / g1, t2 = ta2 / g1;
+    const R sc = R(1) / (R(1) + t0 * t0 + t1 * t1 + t2 * t2);
+    const R ut = up0 * t0 + up1 * t1 + up2 * t2;
+    u[0] = sc * (up0 + ut * t0 + (up1 * t2 - up2 * t1));
+    u[1] = sc * (up1 + ut * t1 + (up2 * t0 - up0 * t2));
+    u[2] = sc * (up2 + ut * t2 + (up0 * t1 - up1 * t0));
+}
+
+// The momentum update of a species: Boris (pusher 0) or Vay (pusher 1).
+template <typename R>
+__device__ inline void push_momentum(int pusher, R h, const R E[3], const R B[3], R u[3]) {
+    if (pusher == 1) vay<R>(h, E, B, u);
+    else boris<R>(h, E, B, u);
 }
 
 __device__ inline int wrap_index(int i, int n) {

@@ -33,6 +33,10 @@ namespace pic {
 namespace {
 
 constexpr int O = PIC_ORDER;
+
+#ifndef PIC_SKIP_ZERO_ATOMICS
+#define PIC_SKIP_ZERO_ATOMICS 1
+#endif
 using H = Halo<O>;
 
 __device__ inline void flag_range(int *err) { atomicOr(err, 1); }
@@ -227,8 +231,11 @@ __device__ __forceinline__ R interp(const FA &fa, int comp, const GWin<O, R> &wx
 
 // Each component from its own Yee points: E_c is half-shifted along c,
 // B_c along the two other axes.
+// galerkin: along each axis where a component sits at half-integer points
+// the shape is one order lower (the g1 windows are exactly those axes).
 template <int DIM, typename R, class FA>
-__device__ __forceinline__ void gather(const FA &fa, const int c[3], const R f[3], R E[3], R B[3]) {
+__device__ __forceinline__ void gather(const FA &fa, const int c[3], const R f[3], R E[3], R B[3],
+                                       int galerkin) {
     GWin<O, R> g0[3], g1[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
@@ -239,7 +246,8 @@ __device__ __forceinline__ void gather(const FA &fa, const int c[3], const R f[3
             continue;
         }
         g0[d] = gather_window<O, R>(c[d], f[d], 0);
-        g1[d] = gather_window<O, R>(c[d], f[d], 1);
+        if (galerkin) g1[d] = gather_window_galerkin<O, R>(c[d], f[d]);
+        else g1[d] = gather_window<O, R>(c[d], f[d], 1);
     }
     E[0] = interp<DIM>(fa, 0, g1[0], g0[1], g0[2]);
     E[1] = interp<DIM>(fa, 1, g0[0], g1[1], g0[2]);
@@ -264,6 +272,14 @@ __device__ __forceinline__ void deposit(const JA &ja, const int c0[3], const R f
     DWin<O, R> wx = deposit_window<O, R>(c0[0], f0[0], c1[0], f1[0]);
     DWin<O, R> wz = deposit_window<O, R>(c0[2], f0[2], c1[2], f1[2]);
     const R third = R(1.0 / 3.0);
+    // Line weights factor per axis: S0a S0b + (dSa S0b + S0a dSb)/2 + dSa dSb/3
+    // = S0a (S0b + dSb/2) + dSa (S0b/2 + dSb/3) = S0a h_b + dSa q_b.
+    R hx[K], qx[K], hz[K], qz[K];
+#pragma unroll
+    for (int m = 0; m < K; ++m) {
+        hx[m] = wx.S0[m] + R(0.5) * wx.dS[m]; qx[m] = R(0.5) * wx.S0[m] + third * wx.dS[m];
+        hz[m] = wz.S0[m] + R(0.5) * wz.dS[m]; qz[m] = R(0.5) * wz.S0[m] + third * wz.dS[m];
+    }
     // Edges written per line: K-1 in general; when the particle stays in its
     // reference cell along that axis the window's last node carries no
     // weight, the flux through edge K-2 is sum(dS) = 0, and it is skipped.
@@ -284,6 +300,11 @@ __device__ __forceinline__ void deposit(const JA &ja, const int c0[3], const R f
     if (DIM == 3) {
         DWin<O, R> wy = deposit_window<O, R>(c0[1], f0[1], c1[1], f1[1]);
         const int ey = (wy.S0[K - 1] == R(0) && wy.dS[K - 1] == R(0)) ? K - 2 : K - 1;
+        R hy[K], qy[K];
+#pragma unroll
+        for (int m = 0; m < K; ++m) {
+            hy[m] = wy.S0[m] + R(0.5) * wy.dS[m]; qy[m] = R(0.5) * wy.S0[m] + third * wy.dS[m];
+        }
         A py[K - 1];
         {
             R a = R(0);
@@ -300,8 +321,7 @@ __device__ __forceinline__ void deposit(const JA &ja, const int c0[3], const R f
             for (int k = 0; k < K; ++k) {
 #pragma unroll
                 for (int j = 0; j < K; ++j) {
-                    R t = wy.S0[j] * wz.S0[k] + R(0.5) * (wy.dS[j] * wz.S0[k] + wy.S0[j] * wz.dS[k]) +
-                          third * wy.dS[j] * wz.dS[k];
+                    R t = wy.S0[j] * hz[k] + wy.dS[j] * qz[k];
                     if (t == R(0)) continue;
                     A *line = q0 + k * ps + j * rs;
 #pragma unroll
@@ -313,8 +333,7 @@ __device__ __forceinline__ void deposit(const JA &ja, const int c0[3], const R f
             for (int k = 0; k < K; ++k) {
 #pragma unroll
                 for (int i = 0; i < K; ++i) {
-                    R t = wz.S0[k] * wx.S0[i] + R(0.5) * (wz.dS[k] * wx.S0[i] + wz.S0[k] * wx.dS[i]) +
-                          third * wz.dS[k] * wx.dS[i];
+                    R t = wz.S0[k] * hx[i] + wz.dS[k] * qx[i];
                     if (t == R(0)) continue;
                     A *line = q1 + k * ps + i;
 #pragma unroll
@@ -326,8 +345,7 @@ __device__ __forceinline__ void deposit(const JA &ja, const int c0[3], const R f
             for (int j = 0; j < K; ++j) {
 #pragma unroll
                 for (int i = 0; i < K; ++i) {
-                    R t = wx.S0[i] * wy.S0[j] + R(0.5) * (wx.dS[i] * wy.S0[j] + wx.S0[i] * wy.dS[j]) +
-                          third * wx.dS[i] * wy.dS[j];
+                    R t = wx.S0[i] * hy[j] + wx.dS[i] * qy[j];
                     if (t == R(0)) continue;
                     A *line = q2 + j * rs + i;
 #pragma unroll
@@ -341,8 +359,7 @@ __device__ __forceinline__ void deposit(const JA &ja, const int c0[3], const R f
         for (int k = 0; k < K; ++k) {
 #pragma unroll
             for (int j = 0; j < K; ++j) {
-                R t = wy.S0[j] * wz.S0[k] + R(0.5) * (wy.dS[j] * wz.S0[k] + wy.S0[j] * wz.dS[k]) +
-                      third * wy.dS[j] * wz.dS[k];
+                R t = wy.S0[j] * hz[k] + wy.dS[j] * qz[k];
                 if (t == R(0)) continue;
 #pragma unroll
                 for (int i = 0; i < K - 1; ++i)
@@ -353,8 +370,7 @@ __device__ __forceinline__ void deposit(const JA &ja, const int c0[3], const R f
         for (int k = 0; k < K; ++k) {
 #pragma unroll
             for (int i = 0; i < K; ++i) {
-                R t = wz.S0[k] * wx.S0[i] + R(0.5) * (wz.dS[k] * wx.S0[i] + wz.S0[k] * wx.dS[i]) +
-                      third * wz.dS[k] * wx.dS[i];
+                R t = wz.S0[k] * hx[i] + wz.dS[k] * qx[i];
                 if (t == R(0)) continue;
 #pragma unroll
                 for (int j = 0; j < K - 1; ++j)
@@ -365,8 +381,7 @@ __device__ __forceinline__ void deposit(const JA &ja, const int c0[3], const R f
         for (int j = 0; j < K; ++j) {
 #pragma unroll
             for (int i = 0; i < K; ++i) {
-                R t = wx.S0[i] * wy.S0[j] + R(0.5) * (wx.dS[i] * wy.S0[j] + wx.S0[i] * wy.dS[j]) +
-                      third * wx.dS[i] * wy.dS[j];
+                R t = wx.S0[i] * hy[j] + wx.dS[i] * qy[j];
                 if (t == R(0)) continue;
 #pragma unroll
                 for (int k = 0; k < K - 1; ++k)
@@ -381,7 +396,7 @@ __device__ __forceinline__ void deposit(const JA &ja, const int c0[3], const R f
             A *q2 = ja.at(2, wx.base, 0, wz.base);
 #pragma unroll
             for (int k = 0; k < K; ++k) {
-                R t = wz.S0[k] + R(0.5) * wz.dS[k];
+                R t = hz[k];
                 if (t == R(0)) continue;
 #pragma unroll
                 for (int i = 0; i < K - 1; ++i)
@@ -389,7 +404,7 @@ __device__ __forceinline__ void deposit(const JA &ja, const int c0[3], const R f
             }
 #pragma unroll
             for (int i = 0; i < K; ++i) {
-                R t = wx.S0[i] + R(0.5) * wx.dS[i];
+                R t = hx[i];
                 if (t == R(0)) continue;
 #pragma unroll
                 for (int k = 0; k < K - 1; ++k)
@@ -400,8 +415,7 @@ __device__ __forceinline__ void deposit(const JA &ja, const int c0[3], const R f
             for (int k = 0; k < K; ++k) {
 #pragma unroll
                 for (int i = 0; i < K; ++i) {
-                    R a = wx.S0[i] * wz.S0[k] + R(0.5) * (wx.dS[i] * wz.S0[k] + wx.S0[i] * wz.dS[k]) +
-                          third * wx.dS[i] * wz.dS[k];
+                    R a = wx.S0[i] * hz[k] + wx.dS[i] * qz[k];
                     if (a != R(0)) unsafeAtomicAdd(q1 + k * ps + i, cy * (A)a);
                 }
             }
@@ -409,7 +423,7 @@ __device__ __forceinline__ void deposit(const JA &ja, const int c0[3], const R f
         }
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            R t = wz.S0[k] + R(0.5) * wz.dS[k];
+            R t = hz[k];
             if (t == R(0)) continue;
 #pragma unroll
             for (int i = 0; i < K - 1; ++i)
@@ -417,7 +431,7 @@ __device__ __forceinline__ void deposit(const JA &ja, const int c0[3], const R f
         }
 #pragma unroll
         for (int i = 0; i < K; ++i) {
-            R t = wx.S0[i] + R(0.5) * wx.dS[i];
+            R t = hx[i];
             if (t == R(0)) continue;
 #pragma unroll
             for (int k = 0; k < K - 1; ++k)
@@ -428,8 +442,7 @@ __device__ __forceinline__ void deposit(const JA &ja, const int c0[3], const R f
         for (int k = 0; k < K; ++k) {
 #pragma unroll
             for (int i = 0; i < K; ++i) {
-                R a = wx.S0[i] * wz.S0[k] + R(0.5) * (wx.dS[i] * wz.S0[k] + wx.S0[i] * wz.dS[k]) +
-                      third * wx.dS[i] * wz.dS[k];
+                R a = wx.S0[i] * hz[k] + wx.dS[i] * qz[k];
                 if (a != R(0)) ja.add(1, wx.base + i, 0, wz.base + k, cy * (A)a);
             }
         }
@@ -486,7 +499,7 @@ __device__ __forceinline__ void particle(const DevBox &b, const DevSpecies &sp, 
     if (MODE & MODE_PUSH) {
         R E[3], B[3];
         if constexpr (TILED) {
-            gather<DIM, R>(*lf, c0, f0, E, B);
+            gather<DIM, R>(*lf, c0, f0, E, B, sp.galerkin);
         } else {
             GlobalField<FT> g;
 #pragma unroll
@@ -495,10 +508,10 @@ __device__ __forceinline__ void particle(const DevBox &b, const DevSpecies &sp, 
                 g.F[cc + 3] = (const FT *)gf.B[cc] + b.cell_base;
             }
             g.n0 = b.n[0]; g.n1 = b.n[1]; g.n2 = b.n[2]; g.any = any;
-            gather<DIM, R>(g, c0, f0, E, B);
+            gather<DIM, R>(g, c0, f0, E, B, sp.galerkin);
         }
         const R h = (R)(sp.q * b.dt / (2.0 * sp.m));
-        boris<R>(h, E, B, u);
+        push_momentum<R>(sp.pusher, h, E, B, u);
         const R gi = R(1) / sqrt(R(1) + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
         R disp[3];
         bool good = true;
@@ -715,6 +728,18 @@ __device__ __forceinline__ void deposit_converged(const JA &ja, const int c0[3],
     DWin<O, R> wy;
     if (DIM == 3) wy = deposit_window<O, R>(c0[1], f0[1], c1[1], f1[1]);
     const R third = R(1.0 / 3.0);
+    // factored line weights, as in deposit()
+    R hx[K], qx[K], hy[K], qy[K], hz[K], qz[K];
+#pragma unroll
+    for (int m = 0; m < K; ++m) {
+        hx[m] = wx.S0[m] + R(0.5) * wx.dS[m]; qx[m] = R(0.5) * wx.S0[m] + third * wx.dS[m];
+        hz[m] = wz.S0[m] + R(0.5) * wz.dS[m]; qz[m] = R(0.5) * wz.S0[m] + third * wz.dS[m];
+        if (DIM == 3) {
+            hy[m] = wy.S0[m] + R(0.5) * wy.dS[m]; qy[m] = R(0.5) * wy.S0[m] + third * wy.dS[m];
+        } else {
+            hy[m] = R(0); qy[m] = R(0);
+        }
+    }
     const bool lastx = !(wx.S0[K - 1] == R(0) && wx.dS[K - 1] == R(0));
     const bool lastz = !(wz.S0[K - 1] == R(0) && wz.dS[K - 1] == R(0));
     const bool lasty = DIM == 3 && !(wy.S0[K - 1] == R(0) && wy.dS[K - 1] == R(0));
@@ -774,8 +799,13 @@ __device__ __forceinline__ void deposit_converged(const JA &ja, const int c0[3],
             }
         } else {
 #pragma unroll
-            for (int e = 0; e < K - 1; ++e)
+            for (int e = 0; e < K - 1; ++e) {
+#if PIC_SKIP_ZERO_ATOMICS
                 if (e < ne && v[e] != PV(0)) unsafeAtomicAdd(base + e * stride, (A)v[e]);
+#else
+                if (e < ne) unsafeAtomicAdd(base + e * stride, (A)v[e]);
+#endif
+            }
         }
     };
     auto put = [&](A *addr, R v) {
@@ -799,8 +829,7 @@ __device__ __forceinline__ void deposit_converged(const JA &ja, const int c0[3],
         for (int k = 0; k < K; ++k) {
 #pragma unroll
             for (int j = 0; j < K; ++j) {
-                R t = wy.S0[j] * wz.S0[k] + R(0.5) * (wy.dS[j] * wz.S0[k] + wy.S0[j] * wz.dS[k]) +
-                      third * wy.dS[j] * wz.dS[k];
+                R t = wy.S0[j] * hz[k] + wy.dS[j] * qz[k];
                 if (!wave_any(t != R(0))) continue;
                 line_put(q0 + k * ps + j * rs, 1, px, t, exu);
             }
@@ -809,8 +838,7 @@ __device__ __forceinline__ void deposit_converged(const JA &ja, const int c0[3],
         for (int k = 0; k < K; ++k) {
 #pragma unroll
             for (int i = 0; i < K; ++i) {
-                R t = wz.S0[k] * wx.S0[i] + R(0.5) * (wz.dS[k] * wx.S0[i] + wz.S0[k] * wx.dS[i]) +
-                      third * wz.dS[k] * wx.dS[i];
+                R t = wz.S0[k] * hx[i] + wz.dS[k] * qx[i];
                 if (!wave_any(t != R(0))) continue;
                 line_put(q1 + k * ps + i, rs, py, t, eyu);
             }
@@ -819,8 +847,7 @@ __device__ __forceinline__ void deposit_converged(const JA &ja, const int c0[3],
         for (int j = 0; j < K; ++j) {
 #pragma unroll
             for (int i = 0; i < K; ++i) {
-                R t = wx.S0[i] * wy.S0[j] + R(0.5) * (wx.dS[i] * wy.S0[j] + wx.S0[i] * wy.dS[j]) +
-                      third * wx.dS[i] * wy.dS[j];
+                R t = wx.S0[i] * hy[j] + wx.dS[i] * qy[j];
                 if (!wave_any(t != R(0))) continue;
                 line_put(q2 + j * rs + i, ps, pz, t, ezu);
             }
@@ -831,13 +858,13 @@ __device__ __forceinline__ void deposit_converged(const JA &ja, const int c0[3],
         A *q2 = ja.at(2, wx.base, 0, wz.base);
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            R t = wz.S0[k] + R(0.5) * wz.dS[k];
+            R t = hz[k];
             if (!wave_any(t != R(0))) continue;
             line_put(q0 + k * ps, 1, px, t, exu);
         }
 #pragma unroll
         for (int i = 0; i < K; ++i) {
-            R t = wx.S0[i] + R(0.5) * wx.dS[i];
+            R t = hx[i];
             if (!wave_any(t != R(0))) continue;
             line_put(q2 + i, ps, pz, t, ezu);
         }
@@ -846,8 +873,7 @@ __device__ __forceinline__ void deposit_converged(const JA &ja, const int c0[3],
         for (int k = 0; k < K; ++k) {
 #pragma unroll
             for (int i = 0; i < K; ++i) {
-                R a = wx.S0[i] * wz.S0[k] + R(0.5) * (wx.dS[i] * wz.S0[k] + wx.S0[i] * wz.dS[k]) +
-                      third * wx.dS[i] * wz.dS[k];
+                R a = wx.S0[i] * hz[k] + wx.dS[i] * qz[k];
                 if (!wave_any(a != R(0))) continue;
                 put(q1 + k * ps + i, cy * a);
             }
@@ -887,10 +913,10 @@ __device__ __forceinline__ void particle_converged(const DevBox &b, const DevSpe
         u[0] = ua[0][i]; u[1] = ua[1][i]; u[2] = ua[2][i];
     }
     R E[3], B[3];
-    gather<DIM, R>(lf, c0, f0, E, B);
+    gather<DIM, R>(lf, c0, f0, E, B, sp.galerkin);
     const R dt = (R)b.dt;
     const R h = (R)(sp.q * b.dt / (2.0 * sp.m));
-    boris<R>(h, E, B, u);
+    push_momentum<R>(sp.pusher, h, E, B, u);
     const R gi = R(1) / sqrt(R(1) + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
     R disp[3];
     bool good = true;
@@ -1264,12 +1290,13 @@ hipError_t launch_tiled_q(const KParams &prm, int dims, int grid, int block, siz
 }
 
 // Fused kernels: per dimensionality, with quad pooling of the deposit when
-// the lane stride is 1.  Push-only / deposit-only kernels: mixed form.
+// lane stride 1 meets the quads-first order (prm.quad).  Push-only /
+// deposit-only kernels: mixed form.
 template <class P, int MODE, bool PERS>
 hipError_t launch_tiled_dims(const KParams &prm, int dims, int grid, int block, size_t lds,
                              hipStream_t st) {
     if constexpr (MODE == MODE_FUSED) {
-        if (prm.lane_stride <= 1) return launch_tiled_q<P, MODE, PERS, true>(prm, dims, grid, block, lds, st);
+        if (prm.quad) return launch_tiled_q<P, MODE, PERS, true>(prm, dims, grid, block, lds, st);
         return launch_tiled_q<P, MODE, PERS, false>(prm, dims, grid, block, lds, st);
     }
     hipLaunchKernelGGL((k_tiled<P, MODE, PERS, 0, false>), dim3(grid), dim3(block), lds, st, prm);

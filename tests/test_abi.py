@@ -60,7 +60,7 @@ def test_pic_init_rejects_bad_boxes_on_the_host(kw, status):
 
 
 @pytest.mark.parametrize("kw", [dict(block=96), dict(block=2048), dict(lane_stride=65),
-                                dict(cell_order=4), dict(cell_order=-2), dict(pad=3),
+                                dict(cell_order=5), dict(cell_order=-2), dict(pad=3),
                                 dict(pad=-2), dict(quad_spread=2), dict(wg_per_cu=65),
                                 dict(margin=1), dict(margin=-2),
                                 dict(kernel=3)])

@@ -96,3 +96,18 @@ def test_graph_cache_survives_scratch_growth(prec):
             assert rel_l2(ux, uy) <= tol, k
     for c in (cg, ce):
         pic.pic_free(c)
+
+
+@pytest.mark.parametrize("prec", (pic.PIC_FP64, pic.PIC_FP32_SPLIT))
+def test_slice_moments_match_oracle(prec):
+    wl = pi.uniform_box((7, 6, 11), 4, 0.05, 0.3, 2, 4500, "cpu", tile=(4, 4, 4),
+                        species=("e", "i"))
+    box = wl.boxes[0]
+    g = oracle.make_grid(box.dim, box.n, box.dx, box.dt, box.order)
+    run = GpuRun(wl, prec)
+    out = pic.pic_slice_moments(run.ctx, run.sp, 0, box.n[2]).cpu().numpy()
+    run.check()
+    for s, p in enumerate(wl.species):
+        ref = oracle.slice_moments(g, p.numpy())
+        np.testing.assert_allclose(out[s], ref, rtol=1e-12, atol=1e-18)
+    run.free()

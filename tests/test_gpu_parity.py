@@ -160,6 +160,8 @@ def _oracle_sort(box, ref, cell_order):
             perm_o = np.zeros(0, np.int32)
         elif cell_order == 3:
             perm_o = oracle.stable_perm(oracle.tile_cell_keys(_grid(box), box.tile, cb, ref))
+        elif cell_order == 4:
+            perm_o = oracle.rank_major(oracle.tile_cell_keys(_grid(box), box.tile, cb, ref), cb, 4)
         else:
             ck = oracle.cell_order_keys(_grid(box), box.tile, cb, ref)
             perm_o = oracle.quad_order(ck, cb) if cell_order == 2 else oracle.stable_perm(ck)
@@ -168,7 +170,7 @@ def _oracle_sort(box, ref, cell_order):
 
 @pytest.mark.parametrize("case", ["random", "one_tile", "sparse", "ragged2d", "empty"])
 @pytest.mark.parametrize("prec", (pic.PIC_FP64, pic.PIC_FP32_SPLIT))
-@pytest.mark.parametrize("cell_order", (-1, 1, 2, 3))
+@pytest.mark.parametrize("cell_order", (-1, 1, 2, 3, 4))
 def test_sort_bit_exact(case, prec, cell_order):
     seeds = {"random": 1, "one_tile": 2, "sparse": 3, "ragged2d": 4, "empty": 5}
     rng = np.random.default_rng(seeds[case])
@@ -209,7 +211,7 @@ def test_sort_bit_exact(case, prec, cell_order):
     run.free()
 
 
-@pytest.mark.parametrize("cell_order", (-1, 1, 2, 3))
+@pytest.mark.parametrize("cell_order", (-1, 1, 2, 3, 4))
 def test_sort_large_multi_pass(cell_order):
     """~2 M particles, 2^15 tiles: two radix passes (tile id) or three (with
     the cell order), many sort blocks."""

@@ -143,3 +143,29 @@ def test_gather_2d_equals_3d_with_one_y_cell(o):
         E3, B3 = oracle.gather(g3, E, B, xi)
         assert np.allclose(E2, E3, rtol=0, atol=1e-13)
         assert np.allclose(B2, B3, rtol=0, atol=1e-13)
+
+
+def test_rank_major_order_against_python_sorted():
+    # brute force: sort by key (stable), rank within equal keys, then by
+    # (tile, min(rank, 15)) keeping that order for ties
+    rng = np.random.default_rng(21)
+    cb = 3
+    key = (rng.integers(0, 5, 400) << cb) | rng.integers(0, 8, 400)
+    key = key.astype(np.int64)
+    perm = oracle.rank_major(key, cb, 4)
+    srt = sorted(range(len(key)), key=lambda i: key[i])
+    rank = {}
+    seen = {}
+    for i in srt:
+        rank[i] = min(seen.get(key[i], 0), 15)
+        seen[key[i]] = seen.get(key[i], 0) + 1
+    pos = {i: p for p, i in enumerate(srt)}
+    expect = sorted(srt, key=lambda i: ((key[i] >> cb), rank[i], pos[i]))
+    assert list(perm) == expect
+    # consecutive particles of one rank in one tile sit in increasing cells
+    t, c = key[perm] >> cb, key[perm] & 7
+    r = np.array([rank[i] for i in perm])
+    same = (t[1:] == t[:-1]) & (r[1:] == r[:-1])
+    below_cap = same & (r[1:] < 15)
+    assert np.all(c[1:][below_cap] > c[:-1][below_cap])
+    assert np.all(c[1:][same] >= c[:-1][same])
