@@ -287,6 +287,19 @@ pic_status pic_div_edge(pic_ctx *ctx, int32_t box, double *const v[3],
 pic_status pic_energy(pic_ctx *ctx, const pic_fields *f, const pic_species *sp,
                       int32_t nsp, int32_t box, double *out);
 
+/* pic_energy for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving or diagnostics loops, harnesses that forbid
+ * hipMalloc.  Same arguments, results and errors as pic_energy (bit-equal:
+ * the same kernels and summation order), but it allocates nothing: its
+ * partial sums live in a fixed 144 KiB device array of the library, one copy
+ * per GPU, looked up once by pic_init and held until the process ends.  The
+ * array bounds the call to at most 16 species (PIC_ERR_ARG beyond; the cell
+ * and particle counts are not bounded).  Every call on one GPU shares that
+ * GPU's array, and each call overwrites the slots it reads: calls that
+ * overlap in time on one GPU (several streams or threads) race and must be
+ * ordered by the caller. */
+pic_status pic_energy_noalloc(pic_ctx *ctx, const pic_fields *f, const pic_species *sp,
+                              int32_t nsp, int32_t box, double *out);
 
 /* Decomposition of one periodic box into slabs along z, the boxes of this
  * context: the domain decomposition of the paper's multi-GPU runs (Sec.

@@ -26,7 +26,7 @@ PIC_FP64, PIC_FP32_SPLIT = 0, 1
 PIC_KERNEL_DIRECT, PIC_KERNEL_TILED, PIC_KERNEL_BATCHED = 0, 1, 2
 
 EXPORTED = ["pic_init", "pic_sort_tiles", "pic_gather_push", "pic_deposit_J", "pic_advance",
-            "pic_fdtd_step", "pic_step", "pic_deposit_rho", "pic_div_edge", "pic_energy", "pic_slab_fill_guards", "pic_slab_reduce_j",
+            "pic_fdtd_step", "pic_step", "pic_deposit_rho", "pic_div_edge", "pic_energy", "pic_energy_noalloc", "pic_slab_fill_guards", "pic_slab_reduce_j",
             "pic_slab_migrate", "pic_set_absorber", "pic_antenna_add", "pic_window_shift",
             "pic_window_offset", "pic_es_solve", "pic_es_push", "pic_slice_moments", "pic_check",
             "pic_free", "pic_status_str", "pic_last_error", "pic_device_cus", "pic_set_timing",
@@ -88,6 +88,7 @@ def lib():
         L.pic_deposit_rho.argtypes = [P, C.POINTER(pic_species), I, I, P]
         L.pic_div_edge.argtypes = [P, I, P, P]
         L.pic_energy.argtypes = [P, C.POINTER(pic_fields), C.POINTER(pic_species), I, I, P]
+        L.pic_energy_noalloc.argtypes = [P, C.POINTER(pic_fields), C.POINTER(pic_species), I, I, P]
         L.pic_slab_fill_guards.argtypes = [P, C.POINTER(pic_fields), I]
         L.pic_slab_reduce_j.argtypes = [P, C.POINTER(pic_fields), I]
         L.pic_slab_migrate.argtypes = [P, C.POINTER(pic_species), I, I, P, P]
@@ -339,6 +340,15 @@ def pic_energy(ctx, fields: DeviceFields, species, box: int = 0, out: torch.Tens
     f = fields.c()
     _check(lib().pic_energy(ctx, C.byref(f), _species_array(species), len(species), box,
                             _ptr(out)))
+    return out
+
+
+def pic_energy_noalloc(ctx, fields: DeviceFields, species, box: int, out: torch.Tensor):
+    """``pic_energy`` without any device allocation: ``out`` (2 + nsp FP64
+    on the device) must be given; at most 16 species."""
+    f = fields.c()
+    _check(lib().pic_energy_noalloc(ctx, C.byref(f), _species_array(species), len(species), box,
+                                    _ptr(out)))
     return out
 
 

@@ -10,6 +10,7 @@
 #include <cstring>
 #include <algorithm>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -20,6 +21,12 @@
 
 using namespace pic;
 
+// Device memory of pic_energy_noalloc: the per-block partial sums of the
+// energy reductions for up to ENERGY_MAX_SPECIES species (144 KiB), one copy
+// per GPU, held until the process ends.  Host code never uses this name as
+// an address: pic_init looks up each device's copy once
+// (hipGetSymbolAddress) and keeps the pointer per device.
+static __device__ __align__(256) double scratch[(2 + ENERGY_MAX_SPECIES) * ENERGY_MAX_GRID];
 
 namespace {
 
@@ -141,8 +148,9 @@ struct pic_ctx {
     int clock_khz = 0;
     bool capturing = false;
     hipStream_t cap_stream = nullptr;   // private stream graphs are recorded on
-    // partial sums of pic_energy
+    // partial sums of pic_energy; this device's copy of `scratch`
     double *energy_part = nullptr;
+    double *noalloc_part = nullptr;
     size_t energy_cap = 0;
     // z-slab particle migration: direction flags and their prefixes (6 x
     // mig_cap ints), scan scratch, per-species totals (3 each) and per
@@ -181,6 +189,27 @@ int key_bits(int nkeys) {
 void drop_graphs(pic_ctx *c) {
     for (auto &kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
     c->graphs.clear();
+}
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[MAX_DEVICES] = {};
+
+// Address of this device's copy of `scratch`; looked up once per device,
+// with that device current.
+pic_status noalloc_scratch(int dev, double **out) {
+    *out = nullptr;
+    if (dev < 0 || dev >= MAX_DEVICES) return fail(PIC_ERR_DEVICE, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(PIC_ERR_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_ptr[dev] = (double *)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return PIC_OK;
 }
 
 pic_status check_box(const pic_box_desc &b, int i) {
@@ -1161,6 +1190,10 @@ pic_status pic_init(pic_ctx **out, const pic_box_desc *boxes, int32_t nboxes, pi
         delete c;
         return fail(PIC_ERR_DEVICE, "no HIP device");
     }
+    if ((st = noalloc_scratch(dev, &c->noalloc_part)) != PIC_OK) {
+        delete c;
+        return st;
+    }
     const int o = c->order;
     const size_t fb = prec == PIC_FP64 ? 8 : 4;
     c->hfp.assign(nboxes + 1, 0);
@@ -1463,6 +1496,23 @@ pic_status pic_energy(pic_ctx *c, const pic_fields *f, const pic_species *sp, in
     KParams k = make_params(c, f, 0);
     HIP_TRY(launch_energy(c->prec == PIC_FP64 ? 0 : 1, k.f, c->dbox, box, c->hbox[box].ncells, es,
                           nsp, c->energy_part, out, c->stream));
+    return PIC_OK;
+}
+
+pic_status pic_energy_noalloc(pic_ctx *c, const pic_fields *f, const pic_species *sp,
+                              int32_t nsp, int32_t box, double *out) {
+    EnergySp es[ENERGY_MAX_SPECIES];
+    pic_status st = energy_args(c, f, sp, nsp, box, out, es);
+    if (st != PIC_OK) return st;
+    if (!c->noalloc_part) return fail(PIC_ERR_STATE, "no device scratch for this context");
+    DevFields df;
+    for (int d = 0; d < 3; ++d) {
+        df.E[d] = f->E[d];
+        df.B[d] = f->B[d];
+        df.J[d] = f->J[d];
+    }
+    HIP_TRY(launch_energy(c->prec == PIC_FP64 ? 0 : 1, df, c->dbox, box, c->hbox[box].ncells, es,
+                          nsp, c->noalloc_part, out, c->stream));
     return PIC_OK;
 }
 
