@@ -1261,7 +1261,7 @@ pic_status pic_init(pic_ctx **out, const pic_box_desc *boxes, int32_t nboxes, pi
             const pic_box_desc &b = boxes[i];
             size_t by = 0;
             for (int c = 0; c < (field ? 6 : 3); ++c) {
-                size_t n = field ? fb : 8;         // the current tile is FP64 in both forms
+                size_t n = field ? fb : 8;         // FP64 or 64-bit fixed point
                 for (int k = 0; k < 3; ++k) {
                     if (b.dim == 2 && k == 1) continue;
                     const int st = comp_stagger(c, k);

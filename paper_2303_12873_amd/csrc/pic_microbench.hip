@@ -7,6 +7,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace {
 
 constexpr int MB_BLOCK = 512;
@@ -46,7 +48,10 @@ __global__ void __launch_bounds__(MB_BLOCK) k_lds_atomic(int iters, int pattern,
     const T v = T(1);
     for (int it = 0; it < iters; ++it) {
 #pragma unroll
-        for (int u = 0; u < 8; ++u) unsafeAtomicAdd(&lds[s + u * 8], v);
+        for (int u = 0; u < 8; ++u) {
+            if constexpr (std::is_integral<T>::value) atomicAdd(&lds[s + u * 8], v);
+            else unsafeAtomicAdd(&lds[s + u * 8], v);
+        }
     }
     __syncthreads();
     if (threadIdx.x == 0) out[blockIdx.x] = lds[s];
@@ -103,13 +108,18 @@ float time_ms(F launch, int reps) {
 extern "C" {
 
 // LDS atomics (kind 0) or reads (kind 1) of FP32 (bytes 4) or FP64
-// (bytes 8): `blocks` workgroups of 512 threads, each lane issuing 8 * iters
-// operations.  Returns ms per launch.
+// (bytes 8), or integer atomic adds (kind 2) of 32-bit (bytes 4) or 64-bit
+// (bytes 8) integers: `blocks` workgroups of 512 threads, each lane issuing
+// 8 * iters operations.  Returns ms per launch.
 float pic_mb_lds(int kind, int bytes, int pattern, int blocks, int iters) {
     void *out = nullptr;
     if (hipMalloc(&out, (size_t)blocks * 8) != hipSuccess) return -1.0f;
     float ms;
-    if (kind == 0 && bytes == 4)
+    if (kind == 2 && bytes == 4)
+        ms = time_ms([&] { hipLaunchKernelGGL(k_lds_atomic<unsigned int>, dim3(blocks), dim3(MB_BLOCK), 0, 0, iters, pattern, (unsigned int *)out); }, 3);
+    else if (kind == 2)
+        ms = time_ms([&] { hipLaunchKernelGGL(k_lds_atomic<unsigned long long>, dim3(blocks), dim3(MB_BLOCK), 0, 0, iters, pattern, (unsigned long long *)out); }, 3);
+    else if (kind == 0 && bytes == 4)
         ms = time_ms([&] { hipLaunchKernelGGL(k_lds_atomic<float>, dim3(blocks), dim3(MB_BLOCK), 0, 0, iters, pattern, (float *)out); }, 3);
     else if (kind == 0)
         ms = time_ms([&] { hipLaunchKernelGGL(k_lds_atomic<double>, dim3(blocks), dim3(MB_BLOCK), 0, 0, iters, pattern, (double *)out); }, 3);

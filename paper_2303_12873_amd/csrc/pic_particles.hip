@@ -18,7 +18,8 @@
 //
 // Precision policies: F64 (FP64 positions, momenta, fields, LDS J) and
 // Split (int32 cell + FP32 in-cell offset, FP32 momenta, fields, gather,
-// push; current accumulated in an FP64 LDS tile, flushed to FP64 J).
+// push, deposit weights; the LDS current tile holds 64-bit fixed-point sums,
+// flushed to FP64 J).
 #include <type_traits>
 
 #include "pic_dev.h"
@@ -74,14 +75,18 @@ __device__ inline int div_exact(int a, int d, double inv_d) {
     return q;
 }
 
-// The LDS current tile is FP64 in both forms: measured on gfx950, an LDS
-// FP32 atomic add wave instruction (ds_add_f32) took ~22x the time of an
-// FP64 one (ds_add_f64) on distinct addresses, and FP64 keeps the tile sum
-// exact to 1e-16.
+// LDS current tile of the split form: 64-bit fixed-point integers with a
+// per-tile power-of-two scale, summed with 64-bit integer LDS atomics and
+// converted to FP64 by the flush.  Measured on gfx950 (wave instruction on
+// distinct addresses): ds_add_f32 ~193 cycles per CU, ds_add_f64 ~8.5,
+// ds_add_u64 ~6.4, and under 2-way bank conflicts 16.7 against 8.6.  Each
+// contribution is an FP32 product truncated at 2^-30 of the tile's largest
+// charge factor (finer than its own FP32 rounding), and integer sums do not
+// depend on the order of the adds.
 struct Split {
     using R = float;
     using FieldT = float;
-    using Acc = double;
+    using Acc = long long;
     static constexpr int PREC = 1;
     static constexpr int MAX_BLOCK = 1024;   // 128 VGPRs: 16 waves per CU
     __device__ static bool load(const DevBox &b, const int *cells, float *const offs[3],
@@ -140,6 +145,7 @@ template <typename T> struct LdsField {
 
 struct GlobalJ {
     static constexpr bool LDS = false;
+    static constexpr bool FIXED = false;
     double *J[3];
     int n0, n1, n2;
     bool any;
@@ -154,16 +160,35 @@ struct GlobalJ {
     }
 };
 
+// One addition into the LDS current tile: an FP64 atomic add, or, for a
+// fixed-point tile, the contribution (already multiplied by the tile's
+// scale, so |v| < 2^31) truncated to an integer and added as a 64-bit
+// integer (ds_add_u64: cheaper than ds_add_f64 and far less sensitive to
+// bank conflicts on gfx950, and order-independent).
+template <typename A, typename V> __device__ __forceinline__ void lds_add(A *p, V v) {
+    if constexpr (std::is_integral<A>::value) {
+        const long long iv = (long long)__float2int_rz((float)v);
+        atomicAdd((unsigned long long *)p, (unsigned long long)iv);
+    } else {
+        unsafeAtomicAdd(p, (A)v);
+    }
+}
+
 template <typename A> struct LdsJ {
     static constexpr bool LDS = true;
+    static constexpr bool FIXED = std::is_integral<A>::value;
     A *base;
     int o0, o1, o2, M0, M1, M012;
+    // fixed point: contributions are scaled by `scale` = 2^s before the
+    // integer add, and the flush multiplies by `unscale` = 2^-s
+    float scale;
+    double unscale;
     __device__ inline A *at(int comp, int i, int j, int k) const {
         return base + comp * M012 + (i - o0) + M0 * ((j - o1) + M1 * (k - o2));
     }
     template <typename V>
     __device__ inline void add(int comp, int i, int j, int k, V v) const {
-        unsafeAtomicAdd(&base[comp * M012 + (i - o0) + M0 * ((j - o1) + M1 * (k - o2))], (A)v);
+        lds_add(&base[comp * M012 + (i - o0) + M0 * ((j - o1) + M1 * (k - o2))], v);
     }
 };
 
@@ -285,9 +310,10 @@ __device__ __forceinline__ void deposit(const JA &ja, const int c0[3], const R f
     // weight, the flux through edge K-2 is sum(dS) = 0, and it is skipped.
     const int ex = (wx.S0[K - 1] == R(0) && wx.dS[K - 1] == R(0)) ? K - 2 : K - 1;
     const int ez = (wz.S0[K - 1] == R(0) && wz.dS[K - 1] == R(0)) ? K - 2 : K - 1;
-    // The products handed to the FP64 atomics are formed in FP64 from the
-    // prefix sums and line weights, so no per-atomic conversion is needed.
-    using A = double;
+    // The products handed to FP64 atomics are formed in FP64 from the prefix
+    // sums and line weights, so no per-atomic conversion is needed; a
+    // fixed-point LDS tile takes them in R (the charge factors arrive scaled).
+    using A = typename std::conditional<JA::FIXED, R, double>::type;
     A px[K - 1], pz[K - 1];
     {
         R a = R(0), c = R(0);
@@ -314,19 +340,19 @@ __device__ __forceinline__ void deposit(const JA &ja, const int c0[3], const R f
         if constexpr (JA::LDS) {
             // one base address per component; lines by uniform strides
             const int rs = ja.M0, ps = ja.M0 * ja.M1;
-            A *q0 = ja.at(0, wx.base, wy.base, wz.base);
-            A *q1 = ja.at(1, wx.base, wy.base, wz.base);
-            A *q2 = ja.at(2, wx.base, wy.base, wz.base);
+            auto *q0 = ja.at(0, wx.base, wy.base, wz.base);
+            auto *q1 = ja.at(1, wx.base, wy.base, wz.base);
+            auto *q2 = ja.at(2, wx.base, wy.base, wz.base);
 #pragma unroll
             for (int k = 0; k < K; ++k) {
 #pragma unroll
                 for (int j = 0; j < K; ++j) {
                     R t = wy.S0[j] * hz[k] + wy.dS[j] * qz[k];
                     if (t == R(0)) continue;
-                    A *line = q0 + k * ps + j * rs;
+                    auto *line = q0 + k * ps + j * rs;
 #pragma unroll
                     for (int i = 0; i < K - 1; ++i)
-                        if (i < ex) unsafeAtomicAdd(line + i, px[i] * (A)t);
+                        if (i < ex) lds_add(line + i, px[i] * (A)t);
                 }
             }
 #pragma unroll
@@ -335,10 +361,10 @@ __device__ __forceinline__ void deposit(const JA &ja, const int c0[3], const R f
                 for (int i = 0; i < K; ++i) {
                     R t = wz.S0[k] * hx[i] + wz.dS[k] * qx[i];
                     if (t == R(0)) continue;
-                    A *line = q1 + k * ps + i;
+                    auto *line = q1 + k * ps + i;
 #pragma unroll
                     for (int j = 0; j < K - 1; ++j)
-                        if (j < ey) unsafeAtomicAdd(line + j * rs, py[j] * (A)t);
+                        if (j < ey) lds_add(line + j * rs, py[j] * (A)t);
                 }
             }
 #pragma unroll
@@ -347,10 +373,10 @@ __device__ __forceinline__ void deposit(const JA &ja, const int c0[3], const R f
                 for (int i = 0; i < K; ++i) {
                     R t = wx.S0[i] * hy[j] + wx.dS[i] * qy[j];
                     if (t == R(0)) continue;
-                    A *line = q2 + j * rs + i;
+                    auto *line = q2 + j * rs + i;
 #pragma unroll
                     for (int k = 0; k < K - 1; ++k)
-                        if (k < ez) unsafeAtomicAdd(line + k * ps, pz[k] * (A)t);
+                        if (k < ez) lds_add(line + k * ps, pz[k] * (A)t);
                 }
             }
             return;
@@ -391,16 +417,16 @@ __device__ __forceinline__ void deposit(const JA &ja, const int c0[3], const R f
     } else {
         if constexpr (JA::LDS) {
             const int ps = ja.M0 * ja.M1;
-            A *q0 = ja.at(0, wx.base, 0, wz.base);
-            A *q1 = ja.at(1, wx.base, 0, wz.base);
-            A *q2 = ja.at(2, wx.base, 0, wz.base);
+            auto *q0 = ja.at(0, wx.base, 0, wz.base);
+            auto *q1 = ja.at(1, wx.base, 0, wz.base);
+            auto *q2 = ja.at(2, wx.base, 0, wz.base);
 #pragma unroll
             for (int k = 0; k < K; ++k) {
                 R t = hz[k];
                 if (t == R(0)) continue;
 #pragma unroll
                 for (int i = 0; i < K - 1; ++i)
-                    if (i < ex) unsafeAtomicAdd(q0 + k * ps + i, px[i] * (A)t);
+                    if (i < ex) lds_add(q0 + k * ps + i, px[i] * (A)t);
             }
 #pragma unroll
             for (int i = 0; i < K; ++i) {
@@ -408,7 +434,7 @@ __device__ __forceinline__ void deposit(const JA &ja, const int c0[3], const R f
                 if (t == R(0)) continue;
 #pragma unroll
                 for (int k = 0; k < K - 1; ++k)
-                    if (k < ez) unsafeAtomicAdd(q2 + k * ps + i, pz[k] * (A)t);
+                    if (k < ez) lds_add(q2 + k * ps + i, pz[k] * (A)t);
             }
             const A cy = (A)(cq[1] * vy);
 #pragma unroll
@@ -416,7 +442,7 @@ __device__ __forceinline__ void deposit(const JA &ja, const int c0[3], const R f
 #pragma unroll
                 for (int i = 0; i < K; ++i) {
                     R a = wx.S0[i] * hz[k] + wx.dS[i] * qz[k];
-                    if (a != R(0)) unsafeAtomicAdd(q1 + k * ps + i, cy * (A)a);
+                    if (a != R(0)) lds_add(q1 + k * ps + i, cy * (A)a);
                 }
             }
             return;
@@ -629,6 +655,10 @@ __device__ __forceinline__ void particle(const DevBox &b, const DevSpecies &sp, 
             vy = u[1] * gi;
         }
         if constexpr (TILED) {
+            if constexpr (JL::FIXED) {
+#pragma unroll
+                for (int d = 0; d < 3; ++d) cq[d] *= lj->scale;
+            }
             deposit<DIM, R>(*lj, c0, f0, c1, f1, cq, vy);
         } else {
             GlobalJ g;
@@ -750,7 +780,7 @@ __device__ __forceinline__ void deposit_converged(const JA &ja, const int c0[3],
     // factor.  Without quad pooling they are kept in the LDS accumulation
     // type, so a line's products need one conversion (of t), not one per
     // edge; pooled quads combine them in R first.
-    using PV = typename std::conditional<QUAD, R, A>::type;
+    using PV = typename std::conditional<QUAD || JA::FIXED, R, A>::type;
     PV px[K - 1], py[K - 1], pz[K - 1];
     {
         R a = R(0), b = R(0), c = R(0);
@@ -783,7 +813,7 @@ __device__ __forceinline__ void deposit_converged(const JA &ja, const int c0[3],
             const R sc = quad_reduce_scatter(v);
             const int r = threadIdx.x & 3;
             if (pool) {
-                if (r < ne) unsafeAtomicAdd(base + r * stride, (A)sc);
+                if (r < ne) lds_add(base + r * stride, sc);
             } else {
                 // Lane r of the quad adds edge (e + r) mod NE at step e, NE =
                 // K - 1 edges per line: for NE = 4 lanes of one quad that
@@ -794,16 +824,16 @@ __device__ __forceinline__ void deposit_converged(const JA &ja, const int c0[3],
                 for (int e = 0; e < NE; ++e) {
                     const int ed = (e + r) % NE;
                     const R x = ed == 0 ? v[0] : ed == 1 ? v[1] : ed == 2 ? v[2] : v[3];
-                    if (ed < ne && x != R(0)) unsafeAtomicAdd(base + ed * stride, (A)x);
+                    if (ed < ne && x != R(0)) lds_add(base + ed * stride, x);
                 }
             }
         } else {
 #pragma unroll
             for (int e = 0; e < K - 1; ++e) {
 #if PIC_SKIP_ZERO_ATOMICS
-                if (e < ne && v[e] != PV(0)) unsafeAtomicAdd(base + e * stride, (A)v[e]);
+                if (e < ne && v[e] != PV(0)) lds_add(base + e * stride, v[e]);
 #else
-                if (e < ne) unsafeAtomicAdd(base + e * stride, (A)v[e]);
+                if (e < ne) lds_add(base + e * stride, v[e]);
 #endif
             }
         }
@@ -812,12 +842,12 @@ __device__ __forceinline__ void deposit_converged(const JA &ja, const int c0[3],
         if constexpr (QUAD) {
             const R s = quad_sum(v);
             if (pool) {
-                if (lead) unsafeAtomicAdd(addr, (A)s);
+                if (lead) lds_add(addr, s);
             } else if (v != R(0)) {
-                unsafeAtomicAdd(addr, (A)v);
+                lds_add(addr, v);
             }
         } else {
-            if (v != R(0)) unsafeAtomicAdd(addr, (A)v);
+            if (v != R(0)) lds_add(addr, v);
         }
     };
     const int rs = ja.M0, ps = ja.M0 * ja.M1;
@@ -956,6 +986,10 @@ __device__ __forceinline__ void particle_converged(const DevBox &b, const DevSpe
     if (DIM == 2) {
         cq[1] = (R)(sp.q / dV) * wgt;
         vy = u[1] * gi;
+    }
+    if constexpr (JL::FIXED) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) cq[d] *= lj.scale;
     }
     deposit_converged<DIM, QUAD, R>(lj, c0, f0, c1, f1, cq, vy, valid);
     if (!valid) return;
@@ -1121,7 +1155,8 @@ __device__ __forceinline__ void process_range(const KParams &prm, const DevBox &
 }
 
 template <int DIM, class P, int MODE, bool QUAD>
-__device__ __forceinline__ void process_item(const KParams &prm, const Item &it, char *smem) {
+__device__ __forceinline__ void process_item(const KParams &prm, const Item &it, char *smem,
+                                             float *red) {
     using FT = typename P::FieldT;
     using A = typename P::Acc;
     const int box = item_box(prm, it);
@@ -1210,7 +1245,58 @@ __device__ __forceinline__ void process_item(const KParams &prm, const Item &it,
         const int n = 3 * lj.M012;
         for (int idx = tid; idx < n; idx += bs) lj.base[idx] = A(0);
     }
+    constexpr bool FIXED = LdsJ<A>::FIXED && (MODE & MODE_DEPOSIT);
+    if constexpr (FIXED) {
+        // Scale of the fixed-point current tile: the largest |charge factor|
+        // (q w dx_d / (dt dV), and q w / dV for the 2D out-of-plane current)
+        // over the item's particles, rounded up to a power of two, maps to
+        // 2^30.  A contribution is that factor times a prefix sum of shape
+        // differences and a line weight, both at most 1 in magnitude, so it
+        // stays below 2^31 as an integer.  Non-finite weights set the range
+        // flag.
+        float m = 0.0f;
+        bool bad = false;
+        auto scan = [&](int s, int p0, int p1) {
+            const DevSpecies &sp = prm.species[s];
+            const double dV = b.dx[0] * b.dx[1] * b.dx[2];
+            double qb = fabs(sp.q) / dV;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) qb = fmax(qb, fabs(sp.q * b.dx[d] / (b.dt * dV)));
+            const float Q = (float)qb;
+            const float *w = (const float *)sp.w;
+            for (int p = p0 + tid; p < p1; p += bs) {
+                const float x = fabsf(w[p]) * Q;
+                bad = bad || !(x <= 3.0e38f);
+                m = fmaxf(m, x);
+            }
+        };
+        if (it.s >= 0) {
+            scan(it.s, it.p0, it.p1);
+        } else {
+            for (int k = prm.box_sp_off[box]; k < prm.box_sp_off[box + 1]; ++k) {
+                const int s = prm.box_sp[k];
+                const int *off = prm.species[s].tile_off;
+                scan(s, off[it.t], off[it.t + 1]);
+            }
+        }
+        if (bad) flag_range(prm.err);
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+        if ((tid & 63) == 0) red[tid >> 6] = m;
+    }
     __syncthreads();
+    if constexpr (FIXED) {
+        float m = 0.0f;
+        for (int wv = 0; wv < (bs >> 6); ++wv) m = fmaxf(m, red[wv]);
+        int e = 0;
+        (void)frexpf(m, &e);              // m < 2^e
+        e = max(e, -90);
+        lj.scale = ldexpf(1.0f, 30 - e);
+        lj.unscale = ldexp(1.0, e - 30);
+    } else {
+        lj.scale = 1.0f;
+        lj.unscale = 1.0;
+    }
     if (it.s >= 0) {
         process_range<DIM, P, MODE, QUAD>(prm, b, it.s, it.p0, it.p1, tile, lf, lj);
     } else {
@@ -1225,13 +1311,14 @@ __device__ __forceinline__ void process_item(const KParams &prm, const Item &it,
         const int n = 3 * lj.M012;
         RegionWalk w(tid, bs, lj.M0, lj.M1, M2);
         for (int idx = tid; idx < n; idx += bs, w.next()) {
-            A v = lj.base[idx];
+            const A v = lj.base[idx];
             if (v == A(0)) continue;
+            const double jv = FIXED ? (double)v * lj.unscale : (double)v;
             int gi = lj.o0 + w.i, gj = lj.o1 + w.j, gk = lj.o2 + w.k;
             if (any) { gi = wrap_index_any(gi, b.n[0]); gj = wrap_index_any(gj, b.n[1]); gk = wrap_index_any(gk, b.n[2]); }
             else { gi = wrap_index(gi, b.n[0]); gj = wrap_index(gj, b.n[1]); gk = wrap_index(gk, b.n[2]); }
             unsafeAtomicAdd(&prm.f.J[w.c][b.cell_base + gi + (long long)b.n[0] * (gj + (long long)b.n[1] * gk)],
-                            (double)v);
+                            jv);
         }
     }
     __syncthreads();
@@ -1243,6 +1330,7 @@ template <class P, int MODE, bool PERSISTENT, int DIMS, bool QUAD>
 __global__ void __launch_bounds__(P::MAX_BLOCK) k_tiled(KParams prm) {
     extern __shared__ __attribute__((aligned(16))) char smem[];
     __shared__ Item cur;
+    __shared__ float red[P::MAX_BLOCK / 64];
     for (int round = 0;; ++round) {
         Item it;
         if (PERSISTENT) {
@@ -1265,13 +1353,13 @@ __global__ void __launch_bounds__(P::MAX_BLOCK) k_tiled(KParams prm) {
         }
         if (it.p1 <= it.p0) continue;
         if constexpr (DIMS == 3) {
-            process_item<3, P, MODE, QUAD>(prm, it, smem);
+            process_item<3, P, MODE, QUAD>(prm, it, smem, red);
         } else if constexpr (DIMS == 2) {
-            process_item<2, P, MODE, QUAD>(prm, it, smem);
+            process_item<2, P, MODE, QUAD>(prm, it, smem, red);
         } else {
             const DevBox &b = prm.boxes[item_box(prm, it)];
-            if (b.dim == 3) process_item<3, P, MODE, QUAD>(prm, it, smem);
-            else process_item<2, P, MODE, QUAD>(prm, it, smem);
+            if (b.dim == 3) process_item<3, P, MODE, QUAD>(prm, it, smem, red);
+            else process_item<2, P, MODE, QUAD>(prm, it, smem, red);
         }
     }
 }

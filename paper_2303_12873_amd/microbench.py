@@ -1,5 +1,6 @@
 """Hardware-rate microbenchmarks on the current GPU (gfx950): LDS FP32/FP64
-atomic adds and reads under several lane-to-address patterns, global FP64
+and 32/64-bit integer atomic adds and reads under several lane-to-address
+patterns, global FP64
 atomic adds, and HBM copy bandwidth.  ``python -m
 paper_2303_12873_amd.microbench`` prints one JSON line per measurement.
 
@@ -37,7 +38,7 @@ def run(cus: int = 256):
     L = _lib()
     out = []
     blocks, iters = cus * 4, 256
-    for kind, kname in ((0, "lds_atomic_add"), (1, "lds_read")):
+    for kind, kname in ((0, "lds_atomic_add"), (1, "lds_read"), (2, "lds_atomic_add_int")):
         for nbytes in (4, 8):
             for pat in PATTERNS:
                 ms = L.pic_mb_lds(kind, nbytes, pat, blocks, iters)
