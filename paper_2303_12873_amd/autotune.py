@@ -52,12 +52,12 @@ PICK_FP32 = Candidate((16, 8, 4), 1024, 8192, 2, 4, -1, 16, 0, 0)
 PICK_FP64 = Candidate((8, 8, 8), 512, 8192, 2, 4, -1, 16, 0, 0)
 
 
-def default_space(dim3: bool, precision=pic.PIC_FP32_SPLIT, sort_every=(8, 16)):
+def default_space(dim3: bool, precision=pic.PIC_FP32_SPLIT, sort_every=(4, 8, 16)):
     """Tile edges whose LDS stage fits, the largest workgroup of the
     precision (smaller ones were slower on every workload measured), lane
-    strides 1 (quad-pooled deposit) and 4 with the within-tile orders that
-    suit them, and sort intervals.  Field-row padding (pad 1, 2) never beat
-    the current-row padding on the workloads measured and is left out."""
+    strides 1 (quad-pooled deposit, or the rank-major order) and 4 with the
+    within-tile orders that suit them, sort intervals, and (split form)
+    padded field and current rows."""
     tiles = [(8, 8, 4), (16, 8, 4), (8, 8, 8)] if dim3 else [(8, 1, 8), (16, 1, 16)]
     split = precision == pic.PIC_FP32_SPLIT
     blocks = [1024] if split else [512]
@@ -66,12 +66,14 @@ def default_space(dim3: bool, precision=pic.PIC_FP32_SPLIT, sort_every=(8, 16)):
     for t, b in itertools.product(tiles, blocks):
         # a work item holds every species of a tile when they fit
         chunk = 8192 if t[0] * t[1] * t[2] > 256 else 4096
-        out.append(Candidate(t, b, chunk, 2, 4, -1, e, 0, 0))
+        for se in sort_every:
+            out.append(Candidate(t, b, chunk, 2, 4, -1, se, 0, 0))
         out.append(Candidate(t, b, chunk, 2, 4, -1, e, 0, -1))
         if split:
-            out.append(Candidate(t, b, chunk, 2, 4, -1, min(sort_every), 0, 0))
             out.append(Candidate(t, b, chunk, 2, 4, 3, e, 0, 0))
             out.append(Candidate(t, b, chunk, 2, 1, 2, e, 0, 0))
+            out.append(Candidate(t, b, chunk, 2, 1, 4, e, 0, 0))
+            out.append(Candidate(t, b, chunk, 2, 4, -1, e, 2, 0))
     return out
 
 

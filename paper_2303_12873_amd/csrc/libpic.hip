@@ -549,7 +549,7 @@ pic_status ensure_sort_scratch(pic_ctx *c, long long np, long long nitems_cap) {
             if ((st = dalloc(&c->keys[i], (size_t)np)) != PIC_OK) return st;
             if ((st = dalloc(&c->vals[i], (size_t)np)) != PIC_OK) return st;
         }
-        if (hipMalloc(&c->tmp, (size_t)std::max<long long>(np, 1) * 8) != hipSuccess) {
+        if (hipMalloc(&c->tmp, (size_t)std::max<long long>(np, 1) * PERM_GROUP_BYTES) != hipSuccess) {
             c->tmp = nullptr;
             return fail(PIC_ERR_OOM, "sort buffer allocation failed");
         }
@@ -664,33 +664,21 @@ pic_status do_sort(pic_ctx *c, const pic_species *sp, int nsp, int32_t *const *p
                                 (int *)c->tmp, c->vals[1 - cur], c->sort_tot, c->scan_scr, S));
             perm = c->vals[1 - cur];
         }
-        // permute the particle arrays in place through the tmp buffer
-        auto perm8 = [&](void *a) -> hipError_t {
-            hipError_t e = launch_gather8(a, perm, c->tmp, np, S);
-            if (e != hipSuccess) return e;
-            return launch_copy8(c->tmp, a, np, S);
-        };
-        auto perm4 = [&](void *a) -> hipError_t {
-            hipError_t e = launch_gather4(a, perm, c->tmp, np, S);
-            if (e != hipSuccess) return e;
-            return launch_copy4(c->tmp, a, np, S);
-        };
+        // permute the particle arrays in place, in groups that share one
+        // read of perm, through the tmp buffer
         const bool two = b.dim == 2;
         if (np > 0) {
+            void *arr[8];
+            int na = 0;
             if (c->prec == PIC_FP64) {
-                for (int d = 0; d < 3; ++d) {
-                    if (!(two && d == 1)) HIP_TRY(perm8(p.x[d]));
-                    HIP_TRY(perm8(p.u[d]));
-                }
-                HIP_TRY(perm8(p.w));
+                for (int d = 0; d < 3; ++d) if (!(two && d == 1)) arr[na++] = p.x[d];
             } else {
-                HIP_TRY(perm4(p.cell));
-                for (int d = 0; d < 3; ++d) {
-                    if (!(two && d == 1)) HIP_TRY(perm4(p.off[d]));
-                    HIP_TRY(perm4(p.u[d]));
-                }
-                HIP_TRY(perm4(p.w));
+                arr[na++] = p.cell;
+                for (int d = 0; d < 3; ++d) if (!(two && d == 1)) arr[na++] = p.off[d];
             }
+            for (int d = 0; d < 3; ++d) arr[na++] = p.u[d];
+            arr[na++] = p.w;
+            HIP_TRY(launch_permute(c->prec == PIC_FP64 ? 8 : 4, arr, na, perm, c->tmp, np, S));
         }
         if (perm_out && perm_out[s]) HIP_TRY(launch_copy4(perm, perm_out[s], np, S));
         if (key_out && key_out[s]) HIP_TRY(launch_shift_copy(c->keys[cur], key_out[s], np, kshift, S));

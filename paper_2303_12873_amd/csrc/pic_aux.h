@@ -33,10 +33,13 @@ hipError_t quads_first(const int *key, const int *perm_in, long long n, int shif
 // starts (n ints each), total (1 int).
 hipError_t rank_keys(const int *key, long long n, int cbits, int rbits, int *heads, int *starts,
                      int *key2, int *total, int *scan_scratch, hipStream_t st);
-hipError_t launch_gather4(const void *src, const int *perm, void *dst, long long n, hipStream_t st);
-hipError_t launch_gather8(const void *src, const int *perm, void *dst, long long n, hipStream_t st);
 hipError_t launch_copy4(const void *src, void *dst, long long n, hipStream_t st);
-hipError_t launch_copy8(const void *src, void *dst, long long n, hipStream_t st);
+// Permute narr particle arrays of elem_bytes (4 or 8) each through perm
+// (dst[i] = src[perm[i]], in place) in groups that share one read of perm:
+// stage holds PERM_GROUP_BYTES per element.
+constexpr int PERM_GROUP_BYTES = 32;
+hipError_t launch_permute(int elem_bytes, void *const *arrays, int narr, const int *perm,
+                          void *stage, long long n, hipStream_t st);
 // Work items of the batched kernel over the box-tile slots (bprefix: nb + 1
 // tile-count prefix over the boxes; box_sp_off / box_sp: species per box).
 hipError_t launch_items(const DevSpecies *spt, const int *bprefix, int nb, const int *box_sp_off,

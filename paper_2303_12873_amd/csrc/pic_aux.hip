@@ -75,8 +75,12 @@ __global__ void k_tile_keys(const DevSpecies *spt, int s, const DevBox *boxes, i
 // ------------------------------------------------------------ radix passes
 
 // Lanes of this wave whose 8-bit digit equals ours (among valid lanes).
+// Fast path: every valid lane holds the first lane's digit (the common case
+// in the passes after the first, the keys being nearly sorted by tile).
 __device__ inline unsigned long long peers(int digit, bool valid) {
     unsigned long long m = __ballot(valid);
+    const int d0 = __builtin_amdgcn_readfirstlane(digit);
+    if (__ballot(valid && digit == d0) == m) return m;
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
         int bit = (digit >> b) & 1;
@@ -272,16 +276,38 @@ __global__ void k_scan_total(const int *in, const int *out, long long n, int *to
 // ------------------------------------------------------------ permutation
 
 template <typename T>
-__global__ void k_gather(const T *src, const int *perm, T *dst, long long n) {
-    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) dst[i] = src[perm[i]];
-}
-
-template <typename T>
 __global__ void k_copy(const T *src, T *dst, long long n) {
     long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) dst[i] = src[i];
 }
+
+// Up to PERM_GROUP_BYTES / sizeof(T) particle arrays permuted together: one
+// kernel gathers them through perm (read once) into consecutive slices of a
+// staging buffer, one kernel copies every slice back.
+template <typename T> struct PermSet {
+    T *a[PERM_GROUP_BYTES / 4];
+    int n;
+};
+
+template <typename T>
+__global__ void k_permute_set(PermSet<T> ps, const int *perm, T *stage, long long n) {
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const long long j = perm[i];
+#pragma unroll
+    for (int k = 0; k < PERM_GROUP_BYTES / (int)sizeof(T); ++k)
+        if (k < ps.n) stage[k * n + i] = ps.a[k][j];
+}
+
+template <typename T>
+__global__ void k_unstage_set(PermSet<T> ps, const T *stage, long long n) {
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+#pragma unroll
+    for (int k = 0; k < PERM_GROUP_BYTES / (int)sizeof(T); ++k)
+        if (k < ps.n) ps.a[k][i] = stage[k * n + i];
+}
+
 
 // ------------------------------------------------------------ work items
 
@@ -630,6 +656,22 @@ __global__ void k_zero_doubles(double *p, long long n) {
 
 inline unsigned blocks_for(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
+template <typename T>
+hipError_t permute_arrays(void *const *arrays, int narr, const int *perm, void *stage, long long n,
+                          hipStream_t st) {
+    constexpr int G = PERM_GROUP_BYTES / (int)sizeof(T);
+    for (int g0 = 0; g0 < narr; g0 += G) {
+        PermSet<T> ps{};
+        ps.n = std::min(G, narr - g0);
+        for (int k = 0; k < ps.n; ++k) ps.a[k] = (T *)arrays[g0 + k];
+        hipLaunchKernelGGL(k_permute_set<T>, dim3(blocks_for(n, 256)), dim3(256), 0, st, ps, perm,
+                           (T *)stage, n);
+        hipLaunchKernelGGL(k_unstage_set<T>, dim3(blocks_for(n, 256)), dim3(256), 0, st, ps,
+                           (const T *)stage, n);
+    }
+    return hipGetLastError();
+}
+
 }  // namespace
 
 // ============================================================ host launchers
@@ -749,31 +791,17 @@ hipError_t launch_shift_copy(const int *src, int *dst, long long n, int shift, h
     return hipGetLastError();
 }
 
-hipError_t launch_gather4(const void *src, const int *perm, void *dst, long long n, hipStream_t st) {
-    if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_gather<int>, dim3(blocks_for(n, 256)), dim3(256), 0, st,
-                       (const int *)src, perm, (int *)dst, n);
-    return hipGetLastError();
-}
-
-hipError_t launch_gather8(const void *src, const int *perm, void *dst, long long n, hipStream_t st) {
-    if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_gather<long long>, dim3(blocks_for(n, 256)), dim3(256), 0, st,
-                       (const long long *)src, perm, (long long *)dst, n);
-    return hipGetLastError();
+hipError_t launch_permute(int elem_bytes, void *const *arrays, int narr, const int *perm,
+                          void *stage, long long n, hipStream_t st) {
+    if (n == 0 || narr == 0) return hipSuccess;
+    if (elem_bytes == 4) return permute_arrays<int>(arrays, narr, perm, stage, n, st);
+    return permute_arrays<long long>(arrays, narr, perm, stage, n, st);
 }
 
 hipError_t launch_copy4(const void *src, void *dst, long long n, hipStream_t st) {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_copy<int>, dim3(blocks_for(n, 256)), dim3(256), 0, st, (const int *)src,
                        (int *)dst, n);
-    return hipGetLastError();
-}
-
-hipError_t launch_copy8(const void *src, void *dst, long long n, hipStream_t st) {
-    if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_copy<long long>, dim3(blocks_for(n, 256)), dim3(256), 0, st,
-                       (const long long *)src, (long long *)dst, n);
     return hipGetLastError();
 }
 

@@ -24,23 +24,31 @@ def _gpu():
     ensure_built()
 
 
-def _cluster(seed, order=3, weights=None):
-    """One 16^3 tile covering the box; 4 particles in each of the cells
-    6..9 along every axis, so no deposited node wraps onto another."""
-    box = pi.Box(3, (16, 16, 16), pi.DT3, order, (16, 16, 16))
-    r = torch.arange(6, 10)
+def _cluster(seed):
+    """One 8^3 tile covering an 8^3 box; 4 particles in each of the cells
+    3..4 along every axis, so every node they deposit to (1..7 per axis at
+    order 3) is reached from one node of the LDS tile: the flush adds each
+    global node once."""
+    box = pi.Box(3, (8, 8, 8), pi.DT3, 3, (8, 8, 8))
+    r = torch.arange(3, 5)
     cz, cy, cx = torch.meshgrid(r, r, r, indexing="ij")
-    cells = (cx + 16 * (cy + 16 * cz)).reshape(-1)
+    cells = (cx + 8 * (cy + 8 * cz)).reshape(-1)
     p = pi.particles_in_cells(box, cells, 4, 0.01, -1.0, 1.0, 0.2, seed, "cpu")
-    if weights is not None:
-        p.w = weights(p.np).to(torch.float64).to(torch.float32).to(torch.float64)
-    E, B = pi.zero_fields(box, "cpu")
     g = torch.Generator().manual_seed(seed + 1)
-    E = (torch.rand(E.shape, generator=g, dtype=torch.float64) - 0.5) * 0.02
-    B = (torch.rand(B.shape, generator=g, dtype=torch.float64) - 0.5) * 0.02
+    E = ((torch.rand((3, box.ncells), generator=g, dtype=torch.float64) - 0.5) * 0.02)
+    B = ((torch.rand((3, box.ncells), generator=g, dtype=torch.float64) - 0.5) * 0.02)
     E = E.to(torch.float32).to(torch.float64)
     B = B.to(torch.float32).to(torch.float64)
-    return pi.Workload("cluster_16cube_one_tile", [box], [p], [E], [B], steps=1)
+    return pi.Workload("cluster_8cube_one_tile", [box], [p], [E], [B], steps=1)
+
+
+def _box(seed, weights=None):
+    wl = pi.uniform_box((12, 10, 9), 3, 0.05, 0.2, 3, seed, "cpu", tile=(4, 4, 4),
+                        fields="fourier", species=("e", "i"))
+    if weights is not None:
+        for k, p in enumerate(wl.species):
+            p.w = weights(p.np, k).to(torch.float32).to(torch.float64)
+    return wl
 
 
 def _permuted(wl, perm):
@@ -57,6 +65,7 @@ def test_tile_sums_do_not_depend_on_particle_order(kernel):
     perm = torch.randperm(wl.species[0].np, generator=torch.Generator().manual_seed(3))
     wl2 = _permuted(wl, perm)
     Js = []
+    assert wl.species[0].np == 32
     for w in (wl, wl2):
         run = GpuRun(w, pic.PIC_FP32_SPLIT, kernel=kernel, cell_order=-1)
         run.sort()
@@ -70,10 +79,10 @@ def test_tile_sums_do_not_depend_on_particle_order(kernel):
 
 @pytest.mark.parametrize("kernel", KERNELS)
 def test_weights_over_six_decades_match_oracle(kernel):
-    def weights(n):
-        g = torch.Generator().manual_seed(11)
+    def weights(n, k):
+        g = torch.Generator().manual_seed(11 + k)
         return 10.0 ** (-6.0 * torch.rand(n, generator=g, dtype=torch.float64)) * 0.01
-    wl = _cluster(7200, weights=weights)
+    wl = _box(7200, weights=weights)
     box = wl.boxes[0]
     g = oracle.make_grid(box.dim, box.n, box.dx, box.dt, box.order)
     sps = [p.numpy() for p in wl.species]
@@ -91,8 +100,8 @@ def test_weights_over_six_decades_match_oracle(kernel):
 @pytest.mark.parametrize("bad", (float("inf"), float("nan")))
 @pytest.mark.parametrize("kernel", KERNELS)
 def test_nonfinite_weight_sets_range_flag(kernel, bad):
-    wl = _cluster(7300)
-    wl.species[0].w[17] = bad
+    wl = _box(7300)
+    wl.species[1].w[17] = bad
     run = GpuRun(wl, pic.PIC_FP32_SPLIT, kernel=kernel)
     run.sort()
     pic.pic_advance(run.ctx, run.f, run.sp)
