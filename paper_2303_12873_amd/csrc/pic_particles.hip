@@ -167,7 +167,8 @@ struct GlobalJ {
 // bank conflicts on gfx950, and order-independent).
 template <typename A, typename V> __device__ __forceinline__ void lds_add(A *p, V v) {
     if constexpr (std::is_integral<A>::value) {
-        const long long iv = (long long)__float2int_rz((float)v);
+        // a plain conversion: one v_cvt_i32_f32 (rounds toward zero)
+        const long long iv = (long long)(int)(float)v;
         atomicAdd((unsigned long long *)p, (unsigned long long)iv);
     } else {
         unsafeAtomicAdd(p, (A)v);
@@ -1124,19 +1125,24 @@ __device__ __forceinline__ void process_range(const KParams &prm, const DevBox &
                 const int qs = sl >> 2;
                 const int idx = (((qs & 15) * C + (qs >> 4)) << 2) + (sl & 3);
                 const bool have = sl < tot && idx < n;
-                particle_converged<DIM, P, QUAD>(b, sp, (long long)(p0 + (have ? idx : 0)), have,
-                                                 tile, lf, lj, prm.err, prm.strag_count + s);
+                if (wave_any(have))
+                    particle_converged<DIM, P, QUAD>(b, sp, (long long)(p0 + (have ? idx : 0)),
+                                                     have, tile, lf, lj, prm.err,
+                                                     prm.strag_count + s);
             }
             return;
         }
-        // every lane runs the same number of slots (the converged path)
+        // every lane of a wave runs the same slots (the converged path); a
+        // wave without a particle in a round (the last, partial round of a
+        // range) skips it
         const int rounds = (total + bs - 1) / bs;
         for (int rd = 0; rd < rounds; ++rd) {
             const int sl = tid + rd * bs;
             const int idx = r * S + q;
             const bool have = sl < total && idx < n;
-            particle_converged<DIM, P, QUAD>(b, sp, (long long)(p0 + (have ? idx : 0)), have, tile,
-                                             lf, lj, prm.err, prm.strag_count + s);
+            if (wave_any(have))
+                particle_converged<DIM, P, QUAD>(b, sp, (long long)(p0 + (have ? idx : 0)), have,
+                                                 tile, lf, lj, prm.err, prm.strag_count + s);
             r += dr;
             q += dq;
             if (r >= G) { r -= G; q += 1; }
