@@ -624,24 +624,34 @@ pic_status do_sort(pic_ctx *c, const pic_species *sp, int nsp, int32_t *const *p
         // (cell_order 1/2 add two class bits; 3 orders by cell alone)
         int cb = 0;
         const int classes = (c->tun.cell_order == 3 || c->tun.cell_order == 4) ? 0 : 1;
+        const int vol = b.tile[0] * (b.dim == 3 ? b.tile[1] : 1) * b.tile[2];
         if (c->tun.cell_order) {
-            const int vol = b.tile[0] * (b.dim == 3 ? b.tile[1] : 1) * b.tile[2];
             cb = key_bits(vol);
             if (key_bits(nkeys) + cb + 2 * classes > 31) cb = 0;
         }
         const int shift = cb ? cb + 2 * classes : 0;
+        // rank-major with tiles of at most RM_MAXV cells: the radix passes
+        // sort by tile only (from bit cb up) and one wave per tile orders
+        // its particles
+        const bool rm_tiles = cb && c->tun.cell_order == 4 && vol <= RM_MAXV;
+        const int lo = rm_tiles ? cb : 0;
         HIP_TRY(launch_tile_keys(prec, c->dsp, s, np, c->dbox, cb, classes, c->keys[0], c->vals[0],
                                  c->derr, S));
-        const int passes = (key_bits(nkeys) + shift + 7) / 8;
+        const int passes = (key_bits(nkeys) + shift - lo + 7) / 8;
         int cur = 0;
         for (int ps = 0; ps < passes; ++ps) {
             HIP_TRY(radix_pass(c->keys[cur], c->vals[cur], c->keys[1 - cur], c->vals[1 - cur], np,
-                               8 * ps, c->counts, c->scan_scr, S));
+                               lo + 8 * ps, c->counts, c->scan_scr, S));
             cur = 1 - cur;
         }
         const int *perm = c->vals[cur];
         int kshift = shift;
-        if (cb && c->tun.cell_order == 4) {
+        if (rm_tiles) {
+            HIP_TRY(launch_tile_offsets(c->keys[cur], np, nkeys, cb, sl.tile_off, S));
+            HIP_TRY(rank_major_tiles(c->keys[cur], c->vals[cur], sl.tile_off, nkeys, cb, vol,
+                                     c->keys[1 - cur], c->vals[1 - cur], S));
+            perm = c->vals[1 - cur];
+        } else if (cb && c->tun.cell_order == 4) {
             // rank-major: (tile, rank in cell) keys, then stable passes over
             // them (ties stay in cell order)
             int *heads = (int *)c->tmp, *starts = heads + np;
@@ -658,7 +668,7 @@ pic_status do_sort(pic_ctx *c, const pic_species *sp, int nsp, int32_t *const *p
             perm = c->vals[cur];
             kshift = RANK_BITS;
         }
-        HIP_TRY(launch_tile_offsets(c->keys[cur], np, nkeys, kshift, sl.tile_off, S));
+        if (!rm_tiles) HIP_TRY(launch_tile_offsets(c->keys[cur], np, nkeys, kshift, sl.tile_off, S));
         if (cb && c->tun.cell_order == 2) {
             HIP_TRY(quads_first(c->keys[cur], c->vals[cur], np, shift, sl.tile_off, c->keys[1 - cur],
                                 (int *)c->tmp, c->vals[1 - cur], c->sort_tot, c->scan_scr, S));

@@ -31,6 +31,14 @@ hipError_t quads_first(const int *key, const int *perm_in, long long n, int shif
 // Rank-major keys: from sorted (tile << cbits | cell) keys, key2 = tile <<
 // rbits | min(rank within the cell's run, 2^rbits - 1).  Scratch: heads,
 // starts (n ints each), total (1 int).
+// Rank-major order inside every tile from keys sorted by tile (stable) whose
+// low cbits hold the cell within the tile (V cells, at most RM_MAXV): ranks
+// 0 .. RM_RMAX - 1 one per occupied cell, the rest last, by cell; perm_out
+// = perm_in reordered; rank_tmp: n ints of scratch.
+constexpr int RM_RMAX = 15;
+constexpr int RM_MAXV = 1024;
+hipError_t rank_major_tiles(const int *key, const int *perm_in, const int *off, int nkeys,
+                            int cbits, int V, int *rank_tmp, int *perm_out, hipStream_t st);
 hipError_t rank_keys(const int *key, long long n, int cbits, int rbits, int *heads, int *starts,
                      int *key2, int *total, int *scan_scratch, hipStream_t st);
 hipError_t launch_copy4(const void *src, void *dst, long long n, hipStream_t st);

@@ -194,6 +194,100 @@ __global__ void k_rank_keys(const int *key, long long n, const int *heads_excl, 
     key2[i] = ((key[i] >> cbits) << rbits) | rank;
 }
 
+// Rank-major order inside each tile, one wave per tile (grid-stride over
+// tiles).  key: sorted by tile, ties in previous order, low cbits = the
+// cell within the tile; perm_in: previous index of each sorted element;
+// off: tile offsets (nkeys + 1).  An element that is the k-th of its cell
+// c (k counted in sorted order, so in previous order) goes, for k < RMAX,
+// to off[t] + base[k] + (number of cells c' < c holding more than k
+// elements), base[k] = number of elements of ranks below k; the elements
+// of rank >= RMAX follow, by cell and then rank.  This is the stable sort
+// by (tile, min(rank, RMAX), cell) of the previous order.  rank_tmp: n ints
+// of scratch.  LDS: cnt[V] ints, occupancy prefixes [RMAX][V] ushorts, the
+// excess prefix [V] ints, base[RMAX + 1].
+__global__ void __launch_bounds__(64) k_rank_major_tiles(const int *key, const int *perm_in,
+                                                        const int *off, int nkeys, int cbits,
+                                                        int V, int *rank_tmp, int *perm_out) {
+    extern __shared__ int rm_lds[];
+    int *cnt = rm_lds;
+    unsigned short *occ = (unsigned short *)(cnt + V);
+    int *exc = (int *)(occ + RM_RMAX * ((V + 1) & ~1));
+    int *base = exc + V;
+    const int lane = threadIdx.x;
+    const int mask = (1 << cbits) - 1;
+    const unsigned long long below = (1ull << lane) - 1ull;
+    const int cpt = (V + 63) / 64;                 // cells per lane in the scans
+    for (int t = blockIdx.x; t < nkeys; t += gridDim.x) {
+        const int o0 = off[t], o1 = off[t + 1];
+        if (o1 <= o0) continue;
+        for (int c = lane; c < V; c += 64) cnt[c] = 0;
+        __syncthreads();
+        // ranks in sorted order
+        for (int i0 = o0; i0 < o1; i0 += 64) {
+            const int i = i0 + lane;
+            const bool valid = i < o1;
+            const int c = valid ? (key[i] & mask) : 0;
+            unsigned long long m = __ballot(valid);
+            const int c0 = __builtin_amdgcn_readfirstlane(c);
+            if (__ballot(valid && c == c0) != m) {
+                for (int b = 0; b < cbits; ++b) {
+                    const int bit = (c >> b) & 1;
+                    const unsigned long long bal = __ballot(bit);
+                    m &= bit ? bal : ~bal;
+                }
+            }
+            const int r = valid ? cnt[c] + __popcll(m & below) : 0;
+            __syncthreads();
+            if (valid && (m & below) == 0ull) cnt[c] += __popcll(m);
+            if (valid) rank_tmp[i] = r;
+            __syncthreads();
+        }
+        // occupancy prefixes per rank level and the excess prefix
+        int run_tot = 0;
+        for (int k = 0; k <= RM_RMAX; ++k) {
+            int sum = 0;
+            for (int q = 0; q < cpt; ++q) {
+                const int c = lane * cpt + q;
+                if (c < V) sum += k < RM_RMAX ? (cnt[c] > k ? 1 : 0) : max(cnt[c] - RM_RMAX, 0);
+            }
+            // exclusive prefix over the wave's lanes
+            int incl = sum;
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1) {
+                const int y = __shfl_up(incl, d);
+                if (lane >= d) incl += y;
+            }
+            int run = incl - sum;
+            for (int q = 0; q < cpt; ++q) {
+                const int c = lane * cpt + q;
+                if (c >= V) break;
+                if (k < RM_RMAX) {
+                    occ[k * ((V + 1) & ~1) + c] = (unsigned short)run;
+                    run += cnt[c] > k ? 1 : 0;
+                } else {
+                    exc[c] = run;
+                    run += max(cnt[c] - RM_RMAX, 0);
+                }
+            }
+            const int tot = __shfl(incl, 63);
+            if (lane == 0) base[k] = run_tot;
+            run_tot += tot;
+        }
+        __syncthreads();
+        // positions
+        for (int i0 = o0; i0 < o1; i0 += 64) {
+            const int i = i0 + lane;
+            if (i >= o1) break;
+            const int c = key[i] & mask;
+            const int r = rank_tmp[i];
+            const int pos = r < RM_RMAX ? base[r] + occ[r * ((V + 1) & ~1) + c]
+                                        : base[RM_RMAX] + exc[c] + (r - RM_RMAX);
+            perm_out[o0 + pos] = perm_in[i];
+        }
+        __syncthreads();
+    }
+}
+
 __global__ void k_quad_flags(const int *key, long long n, const int *heads_excl, const int *starts,
                              const int *nruns, int *flag) {
     long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -782,6 +876,17 @@ hipError_t rank_keys(const int *key, long long n, int cbits, int rbits, int *hea
     hipLaunchKernelGGL(k_run_starts, dim3(nb), dim3(256), 0, st, key, n, (const int *)heads, starts);
     hipLaunchKernelGGL(k_rank_keys, dim3(nb), dim3(256), 0, st, key, n, (const int *)heads,
                        (const int *)starts, cbits, rbits, key2);
+    return hipGetLastError();
+}
+
+hipError_t rank_major_tiles(const int *key, const int *perm_in, const int *off, int nkeys,
+                            int cbits, int V, int *rank_tmp, int *perm_out, hipStream_t st) {
+    if (V > RM_MAXV || V <= 0) return hipErrorInvalidValue;
+    const size_t lds = (size_t)V * 4 + (size_t)RM_RMAX * ((V + 1) & ~1) * 2 + (size_t)V * 4 +
+                       (RM_RMAX + 1) * 4;
+    const int grid = std::min(nkeys, 65536);
+    hipLaunchKernelGGL(k_rank_major_tiles, dim3(grid), dim3(64), lds, st, key, perm_in, off, nkeys,
+                       cbits, V, rank_tmp, perm_out);
     return hipGetLastError();
 }
 

@@ -234,6 +234,40 @@ def test_sort_large_multi_pass(cell_order):
     run.free()
 
 
+@pytest.mark.parametrize("tile,ppc_mean", (((8, 8, 8), 24.0), ((16, 8, 8), 3.0), ((4, 4, 4), 40.0),
+                                             ((16, 16, 8), 6.0)))
+def test_sort_rank_major_dense(tile, ppc_mean):
+    """Rank-major order with cells holding up to dozens of particles (ranks
+    past the cap of 15 fall into the last level, ordered by cell), in tiles
+    of 64..2048 cells (above 1024 cells the sort takes its general path)."""
+    box = pi.Box(3, (32, 32, 16), pi.DT3, 1, tile)
+    g = torch.Generator().manual_seed(11)
+    counts = torch.poisson(torch.full((box.ncells,), ppc_mean), generator=g).to(torch.int64)
+    counts[::7] = 0
+    p = pi.particles_in_cells(box, torch.arange(box.ncells), counts, 0.01, -1.0, 1.0, 0.01, 78,
+                              "cpu")
+    p = p.select(torch.randperm(p.np, generator=g))
+    wl = pi.Workload("rankdense", [box], [p], [torch.zeros(3, box.ncells, dtype=torch.float64)],
+                     [torch.zeros(3, box.ncells, dtype=torch.float64)])
+    ref = p.numpy()
+    perm_o, key, off_o = _oracle_sort(box, ref, 4)
+    for prec in (pic.PIC_FP64, pic.PIC_FP32_SPLIT):
+        # the sort does not depend on the kernel form; the direct form takes
+        # any tile size
+        run = GpuRun(wl, prec, kernel=pic.PIC_KERNEL_DIRECT, cell_order=4)
+        perm = torch.empty(p.np, dtype=torch.int32, device="cuda")
+        keys = torch.empty(p.np, dtype=torch.int32, device="cuda")
+        offs = torch.empty(box.ntiles + 1, dtype=torch.int32, device="cuda")
+        pic.pic_sort_tiles(run.ctx, run.sp, perm_out=[perm], key_out=[keys], tile_offset_out=[offs])
+        run.check()
+        assert np.array_equal(perm.cpu().numpy(), perm_o)
+        assert np.array_equal(keys.cpu().numpy(), key[perm_o])
+        assert np.array_equal(offs.cpu().numpy(), off_o)
+        x = run.positions_np()
+        assert np.array_equal(x[0], ref.x[0][perm_o])
+        run.free()
+
+
 # ------------------------------------------------------------------ workloads
 
 def test_c1_ten_steps_fp64():
