@@ -805,7 +805,10 @@ __device__ __forceinline__ void deposit_converged(const JA &ja, const int c0[3],
     const bool lead = (threadIdx.x & 3) == 0;
     // One line of up to 4 edges, `ne` of them written (wave-uniform), at
     // addresses base + e * stride.  Pooled quads: lane r adds edge r.
-    auto line_put = [&](A *base, int stride, const PV *pv, R t, int ne) {
+    // rim: the line lies on the last node of the window along one of its two
+    // transverse axes, where a lane whose particle stays in its cell has a
+    // zero weight.
+    auto line_put = [&](A *base, int stride, const PV *pv, R t, int ne, bool rim) {
         PV v[4];
         const PV tv = (PV)t;
 #pragma unroll
@@ -832,7 +835,14 @@ __device__ __forceinline__ void deposit_converged(const JA &ja, const int c0[3],
 #pragma unroll
             for (int e = 0; e < K - 1; ++e) {
 #if PIC_SKIP_ZERO_ATOMICS
-                if (e < ne && v[e] != PV(0)) lds_add(base + e * stride, v[e]);
+                // Zero values are skipped where they are common: on rim lines
+                // and on the last edge of a line (zero for a particle that
+                // stays in its cell along the line).  With the fixed-point
+                // tile the other edges are added without a test (measured
+                // faster on C5: the test and its exec-mask branch cost more
+                // than the rare zero adds); the FP64 tile keeps the test.
+                const bool test = !JA::FIXED || rim || e == K - 2;
+                if (e < ne && (!test || v[e] != PV(0))) lds_add(base + e * stride, v[e]);
 #else
                 if (e < ne) lds_add(base + e * stride, v[e]);
 #endif
@@ -862,7 +872,7 @@ __device__ __forceinline__ void deposit_converged(const JA &ja, const int c0[3],
             for (int j = 0; j < K; ++j) {
                 R t = wy.S0[j] * hz[k] + wy.dS[j] * qz[k];
                 if (!wave_any(t != R(0))) continue;
-                line_put(q0 + k * ps + j * rs, 1, px, t, exu);
+                line_put(q0 + k * ps + j * rs, 1, px, t, exu, j == K - 1 || k == K - 1);
             }
         }
 #pragma unroll
@@ -871,7 +881,7 @@ __device__ __forceinline__ void deposit_converged(const JA &ja, const int c0[3],
             for (int i = 0; i < K; ++i) {
                 R t = wz.S0[k] * hx[i] + wz.dS[k] * qx[i];
                 if (!wave_any(t != R(0))) continue;
-                line_put(q1 + k * ps + i, rs, py, t, eyu);
+                line_put(q1 + k * ps + i, rs, py, t, eyu, i == K - 1 || k == K - 1);
             }
         }
 #pragma unroll
@@ -880,7 +890,7 @@ __device__ __forceinline__ void deposit_converged(const JA &ja, const int c0[3],
             for (int i = 0; i < K; ++i) {
                 R t = wx.S0[i] * hy[j] + wx.dS[i] * qy[j];
                 if (!wave_any(t != R(0))) continue;
-                line_put(q2 + j * rs + i, ps, pz, t, ezu);
+                line_put(q2 + j * rs + i, ps, pz, t, ezu, i == K - 1 || j == K - 1);
             }
         }
     } else {
@@ -891,13 +901,13 @@ __device__ __forceinline__ void deposit_converged(const JA &ja, const int c0[3],
         for (int k = 0; k < K; ++k) {
             R t = hz[k];
             if (!wave_any(t != R(0))) continue;
-            line_put(q0 + k * ps, 1, px, t, exu);
+            line_put(q0 + k * ps, 1, px, t, exu, k == K - 1);
         }
 #pragma unroll
         for (int i = 0; i < K; ++i) {
             R t = hx[i];
             if (!wave_any(t != R(0))) continue;
-            line_put(q2 + i, ps, pz, t, ezu);
+            line_put(q2 + i, ps, pz, t, ezu, i == K - 1);
         }
         const R cy = cq[1] * vy;
 #pragma unroll
