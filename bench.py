@@ -226,6 +226,24 @@ def roofline(np_tot, ncells, order, dim3, prec, kernel_ms, traffic=None, bound=N
     return r
 
 
+# Yee step per cell: algorithmic = read E, B, J once and write E, B once
+# (FP64: 120 B; split: FP32 E/B, FP64 J: 72 B); as run, three streaming
+# passes (B half: read E, B, write B; E: read E, B, J, write E; B half).
+FDTD_BYTES_PER_CELL = {"fp64": 120, "fp32": 72}
+FDTD_PASS_BYTES_PER_CELL = {"fp64": 72 + 96 + 72, "fp32": 36 + 60 + 36}
+
+
+def fdtd_roofline(ncells, prec, ms):
+    """HBM fractions of one pic_fdtd_step over its measured duration."""
+    t = ms * 1e-3
+    alg = ncells * FDTD_BYTES_PER_CELL[prec]
+    run = ncells * FDTD_PASS_BYTES_PER_CELL[prec]
+    return {"ms": round(ms, 4), "algorithmic_bytes": alg,
+            "hbm_frac": round(alg / t / 1e9 / PEAK_HBM_GBS, 4),
+            "bytes_three_passes": run,
+            "hbm_frac_three_passes": round(run / t / 1e9 / PEAK_HBM_GBS, 4)}
+
+
 # ------------------------------------------------------------------ legs
 
 def leg_error(wl, c32, c64, steps):
@@ -506,6 +524,7 @@ def main():
         "breakdown_ms": {"advance": r32["ms_advance"], "advance_min": r32["kernel_ms_min"],
                          "advance_max": r32["kernel_ms_max"], "sort": r32["ms_sort"],
                          "fdtd": r32["ms_fdtd"], "advance_per_step": r32["kernel_ms_steps"]},
+        "fdtd_roofline": fdtd_roofline(ncells, "fp32", r32["ms_fdtd"]),
     }
     if r64 is not None:
         v64 = r64["np"] * 1e3 / r64["ms_step"]
@@ -514,7 +533,8 @@ def main():
                                               "fdtd": r64["ms_fdtd"],
                                               "advance_per_step": r64["kernel_ms_steps"]},
                              "config": launch_config(c64), "sort_every": c64.sort_every,
-                             "autotuned": tuned64}
+                             "autotuned": tuned64,
+                             "fdtd_roofline": fdtd_roofline(r64["cells"], "fp64", r64["ms_fdtd"])}
         out["speedup_fp32_batched_vs_fp64_plain"] = value / v64
     torch.cuda.empty_cache()
     if "error" in legs and not args.no_fp64:

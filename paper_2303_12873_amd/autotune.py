@@ -45,12 +45,12 @@ class Candidate:
 
 # The configurations the autotuner picks on the 256x256x2048 two-species
 # order-3 laser-plasma box: FP32 split batched (16x8x4 tiles, 1024 threads,
-# lane stride 4, tile order, sort every 16 steps) and FP64 plain tiled
-# (16x8x4 tiles, 512 threads, lane stride 4, sort every 4 steps: its larger
-# LDS stage leaves less room for the staged margin, so its stragglers grow
-# faster between sorts).  bench.py times these unless asked to tune, and the
-# full-size parity tests run exactly them.
-PICK_FP32 = Candidate((16, 8, 4), 1024, 8192, 2, 4, -1, 16, 0, 0)
+# lane stride 1 over the rank-major order, sort every 16 steps) and FP64
+# plain tiled (16x8x4 tiles, 512 threads, lane stride 4, sort every 4
+# steps: its larger LDS stage leaves less room for the staged margin, so
+# its stragglers grow faster between sorts).  bench.py times these unless
+# asked to tune, and the full-size parity tests run exactly them.
+PICK_FP32 = Candidate((16, 8, 4), 1024, 8192, 2, 1, 4, 16, 0, 0)
 PICK_FP64 = Candidate((16, 8, 4), 512, 8192, 2, 4, -1, 4, 0, 0)
 
 
@@ -128,11 +128,15 @@ def _run(wl, precision, cand: Candidate, steps: int, stream, warm: int = 4,
 
 def tune(wl, precision=pic.PIC_FP32_SPLIT, space: Optional[List[Candidate]] = None,
          steps: Optional[int] = None, budget_s: float = 120.0,
-         cache: Optional[str] = DEFAULT_CACHE, log=print, kernel: int = pic.PIC_KERNEL_BATCHED):
+         cache: Optional[str] = DEFAULT_CACHE, log=print, kernel: int = pic.PIC_KERNEL_BATCHED,
+         warm: int = 16):
     """Returns (best Candidate, table of (key, ms or reason)).  Each candidate
     runs `steps` whole steps (default: the longest sort interval of the
     space, so every candidate's window holds its sort and the drift after
-    it) after four warm steps."""
+    it) after `warm` steps.  The default of 16 warm steps lets the order of
+    generated inputs (a fixed number of particles per cell, in cell order,
+    which lane stride 4 maps onto distinct cells) fade before the timed
+    window, so the pick reflects the state a run spends most steps in."""
     dim3 = all(b.dim == 3 for b in wl.boxes)
     space = space or default_space(dim3, precision)
     steps = steps or max(c.sort_every for c in space)
@@ -157,7 +161,7 @@ def tune(wl, precision=pic.PIC_FP32_SPLIT, space: Optional[List[Candidate]] = No
             table.append((cand.key(), "skipped: budget"))
             continue
         try:
-            ms, E, J = _run(wl, precision, cand, steps, stream, kernel=kernel)
+            ms, E, J = _run(wl, precision, cand, steps, stream, warm=warm, kernel=kernel)
         except pic.PicError as e:
             table.append((cand.key(), f"rejected: {e}"))
             continue

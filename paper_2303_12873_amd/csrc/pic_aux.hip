@@ -194,39 +194,58 @@ __global__ void k_rank_keys(const int *key, long long n, const int *heads_excl, 
     key2[i] = ((key[i] >> cbits) << rbits) | rank;
 }
 
-// Rank-major order inside each tile, one wave per tile (grid-stride over
-// tiles).  key: sorted by tile, ties in previous order, low cbits = the
-// cell within the tile; perm_in: previous index of each sorted element;
-// off: tile offsets (nkeys + 1).  An element that is the k-th of its cell
-// c (k counted in sorted order, so in previous order) goes, for k < RMAX,
-// to off[t] + base[k] + (number of cells c' < c holding more than k
-// elements), base[k] = number of elements of ranks below k; the elements
-// of rank >= RMAX follow, by cell and then rank.  This is the stable sort
-// by (tile, min(rank, RMAX), cell) of the previous order.  rank_tmp: n ints
-// of scratch.  LDS: cnt[V] ints, occupancy prefixes [RMAX][V] ushorts, the
-// excess prefix [V] ints, base[RMAX + 1].
-__global__ void __launch_bounds__(64) k_rank_major_tiles(const int *key, const int *perm_in,
-                                                        const int *off, int nkeys, int cbits,
-                                                        int V, int *rank_tmp, int *perm_out) {
+// Rank-major order inside each tile, one workgroup of RM_WAVES waves per
+// tile (grid-stride over tiles).  key: sorted by tile, ties in previous
+// order, low cbits = the cell within the tile; perm_in: previous index of
+// each sorted element; off: tile offsets (nkeys + 1).  An element that is
+// the k-th of its cell c (k counted in sorted order, so in previous order)
+// goes, for k < RMAX, to off[t] + base[k] + (number of cells c' < c holding
+// more than k elements), base[k] = number of elements of ranks below k; the
+// elements of rank >= RMAX follow, by cell and then rank.  This is the
+// stable sort by (tile, min(rank, RMAX), cell) of the previous order.
+// rank_tmp: n ints of scratch.  LDS: cnt[V], per-wave chunk counts
+// [RM_WAVES][V], occupancy prefixes [RMAX][V] ushorts, the excess prefix
+// [V], base[RMAX + 1] and the level totals [RMAX + 1].
+constexpr int RM_WAVES = 4;
+constexpr int RM_BATCH = 8;   // chunks of 64 RM_WAVES elements loaded at once
+__global__ void __launch_bounds__(64 * RM_WAVES)
+k_rank_major_tiles(const int *key, const int *perm_in, const int *off, int nkeys, int cbits,
+                   int V, int *rank_tmp, int *perm_out) {
     extern __shared__ int rm_lds[];
+    const int stride = (V + 1) & ~1;
     int *cnt = rm_lds;
-    unsigned short *occ = (unsigned short *)(cnt + V);
-    int *exc = (int *)(occ + RM_RMAX * ((V + 1) & ~1));
+    int *wcnt = cnt + V;
+    unsigned short *occ = (unsigned short *)(wcnt + RM_WAVES * V);
+    int *exc = (int *)(occ + RM_RMAX * stride);
     int *base = exc + V;
-    const int lane = threadIdx.x;
+    int *ltot = base + RM_RMAX + 1;
+    const int tid = threadIdx.x, bs = blockDim.x;
+    const int lane = tid & 63, wave = tid >> 6;
     const int mask = (1 << cbits) - 1;
     const unsigned long long below = (1ull << lane) - 1ull;
     const int cpt = (V + 63) / 64;                 // cells per lane in the scans
     for (int t = blockIdx.x; t < nkeys; t += gridDim.x) {
         const int o0 = off[t], o1 = off[t + 1];
         if (o1 <= o0) continue;
-        for (int c = lane; c < V; c += 64) cnt[c] = 0;
+        for (int c = tid; c < V; c += bs) cnt[c] = 0;
+        for (int c = tid; c < RM_WAVES * V; c += bs) wcnt[c] = 0;
         __syncthreads();
-        // ranks in sorted order
-        for (int i0 = o0; i0 < o1; i0 += 64) {
-            const int i = i0 + lane;
+        // ranks in sorted order, in batches of RM_BATCH chunks whose keys are
+        // loaded first; in chunk i0 wave w takes [i0 + 64 w, i0 + 64 w + 64)
+        for (int b0 = o0; b0 < o1; b0 += RM_BATCH * bs) {
+          int kk[RM_BATCH];
+#pragma unroll
+          for (int u = 0; u < RM_BATCH; ++u) {
+              const int i = b0 + u * bs + tid;
+              kk[u] = i < o1 ? key[i] : 0;
+          }
+#pragma unroll
+          for (int u = 0; u < RM_BATCH; ++u) {
+            const int i0 = b0 + u * bs;
+            if (i0 >= o1) break;
+            const int i = i0 + tid;
             const bool valid = i < o1;
-            const int c = valid ? (key[i] & mask) : 0;
+            const int c = valid ? (kk[u] & mask) : 0;
             unsigned long long m = __ballot(valid);
             const int c0 = __builtin_amdgcn_readfirstlane(c);
             if (__ballot(valid && c == c0) != m) {
@@ -236,53 +255,81 @@ __global__ void __launch_bounds__(64) k_rank_major_tiles(const int *key, const i
                     m &= bit ? bal : ~bal;
                 }
             }
-            const int r = valid ? cnt[c] + __popcll(m & below) : 0;
+            const bool lead = valid && (m & below) == 0ull;
+            if (lead) wcnt[wave * V + c] = __popcll(m);
             __syncthreads();
-            if (valid && (m & below) == 0ull) cnt[c] += __popcll(m);
+            int r = 0;
+            if (valid) {
+                r = cnt[c] + __popcll(m & below);
+                for (int w = 0; w < wave; ++w) r += wcnt[w * V + c];
+            }
+            __syncthreads();
+            if (lead) {
+                atomicAdd(&cnt[c], __popcll(m));
+                wcnt[wave * V + c] = 0;
+            }
             if (valid) rank_tmp[i] = r;
             __syncthreads();
+          }
         }
-        // occupancy prefixes per rank level and the excess prefix
-        int run_tot = 0;
-        for (int k = 0; k <= RM_RMAX; ++k) {
-            int sum = 0;
-            for (int q = 0; q < cpt; ++q) {
-                const int c = lane * cpt + q;
-                if (c < V) sum += k < RM_RMAX ? (cnt[c] > k ? 1 : 0) : max(cnt[c] - RM_RMAX, 0);
-            }
-            // exclusive prefix over the wave's lanes
-            int incl = sum;
-#pragma unroll
-            for (int d = 1; d < 64; d <<= 1) {
-                const int y = __shfl_up(incl, d);
-                if (lane >= d) incl += y;
-            }
-            int run = incl - sum;
-            for (int q = 0; q < cpt; ++q) {
-                const int c = lane * cpt + q;
-                if (c >= V) break;
-                if (k < RM_RMAX) {
-                    occ[k * ((V + 1) & ~1) + c] = (unsigned short)run;
-                    run += cnt[c] > k ? 1 : 0;
-                } else {
-                    exc[c] = run;
-                    run += max(cnt[c] - RM_RMAX, 0);
+        // occupancy prefixes per rank level and the excess prefix: wave w
+        // takes the levels k = w mod RM_WAVES, then thread 0 adds up the
+        // level totals
+        {
+            for (int k = wave; k <= RM_RMAX; k += RM_WAVES) {
+                int sum = 0;
+                for (int q = 0; q < cpt; ++q) {
+                    const int c = lane * cpt + q;
+                    if (c < V) sum += k < RM_RMAX ? (cnt[c] > k ? 1 : 0) : max(cnt[c] - RM_RMAX, 0);
                 }
+                // exclusive prefix over the wave's lanes
+                int incl = sum;
+#pragma unroll
+                for (int d = 1; d < 64; d <<= 1) {
+                    const int y = __shfl_up(incl, d);
+                    if (lane >= d) incl += y;
+                }
+                int run = incl - sum;
+                for (int q = 0; q < cpt; ++q) {
+                    const int c = lane * cpt + q;
+                    if (c >= V) break;
+                    if (k < RM_RMAX) {
+                        occ[k * stride + c] = (unsigned short)run;
+                        run += cnt[c] > k ? 1 : 0;
+                    } else {
+                        exc[c] = run;
+                        run += max(cnt[c] - RM_RMAX, 0);
+                    }
+                }
+                const int tot = __shfl(incl, 63);
+                if (lane == 0) ltot[k] = tot;
             }
-            const int tot = __shfl(incl, 63);
-            if (lane == 0) base[k] = run_tot;
-            run_tot += tot;
         }
         __syncthreads();
-        // positions
-        for (int i0 = o0; i0 < o1; i0 += 64) {
-            const int i = i0 + lane;
-            if (i >= o1) break;
-            const int c = key[i] & mask;
-            const int r = rank_tmp[i];
-            const int pos = r < RM_RMAX ? base[r] + occ[r * ((V + 1) & ~1) + c]
-                                        : base[RM_RMAX] + exc[c] + (r - RM_RMAX);
-            perm_out[o0 + pos] = perm_in[i];
+        if (tid == 0) {
+            int run_tot = 0;
+            for (int k = 0; k <= RM_RMAX; ++k) { base[k] = run_tot; run_tot += ltot[k]; }
+        }
+        __syncthreads();
+        // positions (element i read back by the thread that wrote its rank)
+        for (int b0 = o0; b0 < o1; b0 += RM_BATCH * bs) {
+            int kk[RM_BATCH], rr[RM_BATCH], pp[RM_BATCH];
+#pragma unroll
+            for (int u = 0; u < RM_BATCH; ++u) {
+                const int i = b0 + u * bs + tid;
+                kk[u] = 0; rr[u] = 0; pp[u] = 0;
+                if (i < o1) { kk[u] = key[i]; rr[u] = rank_tmp[i]; pp[u] = perm_in[i]; }
+            }
+#pragma unroll
+            for (int u = 0; u < RM_BATCH; ++u) {
+                const int i = b0 + u * bs + tid;
+                if (i >= o1) continue;
+                const int c = kk[u] & mask;
+                const int r = rr[u];
+                const int pos = r < RM_RMAX ? base[r] + occ[r * stride + c]
+                                            : base[RM_RMAX] + exc[c] + (r - RM_RMAX);
+                perm_out[o0 + pos] = pp[u];
+            }
         }
         __syncthreads();
     }
@@ -882,11 +929,11 @@ hipError_t rank_keys(const int *key, long long n, int cbits, int rbits, int *hea
 hipError_t rank_major_tiles(const int *key, const int *perm_in, const int *off, int nkeys,
                             int cbits, int V, int *rank_tmp, int *perm_out, hipStream_t st) {
     if (V > RM_MAXV || V <= 0) return hipErrorInvalidValue;
-    const size_t lds = (size_t)V * 4 + (size_t)RM_RMAX * ((V + 1) & ~1) * 2 + (size_t)V * 4 +
-                       (RM_RMAX + 1) * 4;
+    const size_t lds = (size_t)V * 4 * (1 + RM_WAVES) + (size_t)RM_RMAX * ((V + 1) & ~1) * 2 +
+                       (size_t)V * 4 + 2 * (RM_RMAX + 1) * 4;
     const int grid = std::min(nkeys, 65536);
-    hipLaunchKernelGGL(k_rank_major_tiles, dim3(grid), dim3(64), lds, st, key, perm_in, off, nkeys,
-                       cbits, V, rank_tmp, perm_out);
+    hipLaunchKernelGGL(k_rank_major_tiles, dim3(grid), dim3(64 * RM_WAVES), lds, st, key, perm_in,
+                       off, nkeys, cbits, V, rank_tmp, perm_out);
     return hipGetLastError();
 }
 
