@@ -296,6 +296,14 @@ def leg_laser(wl, c32, start, steps):
             "kernel_ms_per_step": [round(x, 2) for x in kms]}
 
 
+def _c2_config():
+    from paper_2303_12873_amd.autotune import Candidate
+    # the fastest of a sweep over tiles 4x4x4 .. 16x8x4 (larger ones exceed
+    # the LDS budget in FP64), 256 / 512 threads, tiled and batched kernels,
+    # lane stride 4 / tile order and 1 / rank-major, sort every 8 or 16 steps
+    return Candidate((16, 8, 4), 512, 8192, 2, 4, -1, 8, 0, 0)
+
+
 def leg_c2(steps, warmup):
     import paper_2303_12873_amd as pic
     import pic_inputs as pi
@@ -303,7 +311,7 @@ def leg_c2(steps, warmup):
     import torch
     wl = pi.c2("cuda")
     torch.cuda.synchronize()
-    c64 = Candidate((8, 8, 4), 512, 4096, 2, 4, -1, 16, 0, 0)
+    c64 = _c2_config()
     r = run_form(wl, pic.PIC_FP64, pic.PIC_KERNEL_TILED, c64, steps, warmup)
     roof = roofline(r["np"], r["cells"], 2, True, "fp64", r["ms_advance"], bound="hbm",
                     traffic=measured_traffic(wl.name, launch_config(c64),

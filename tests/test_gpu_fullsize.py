@@ -31,7 +31,7 @@ from pichelp import ensure_built
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
 # bench.py's c2 leg
-C2_FP64 = Candidate((8, 8, 4), 512, 4096, 2, 4, -1, 16, 0, 0)
+C2_FP64 = Candidate((16, 8, 4), 512, 8192, 2, 4, -1, 8, 0, 0)
 
 
 @pytest.fixture(scope="module", autouse=True)

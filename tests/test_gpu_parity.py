@@ -555,11 +555,36 @@ def test_swapped_lane_rows_16_wide(prec, tol, stride, order):
 
 
 @pytest.mark.parametrize("prec,tol", ((pic.PIC_FP64, TOL64), (pic.PIC_FP32_SPLIT, TOL32)))
+def test_rank_major_lane_stride_1_with_resorts(prec, tol):
+    """The split form's launch configuration on the 256x256x2048 box (16x8x4
+    tiles, 1024 threads, lane stride 1 over the rank-major order, chunk
+    8192) on a small two-species box: four steps with a re-sort before the
+    first and the third, fields and particles against the oracle."""
+    wl = pi.uniform_box((32, 16, 12), 4, 0.05, 0.3, 3, 2500, "cpu", tile=(16, 8, 4),
+                        fields="fourier", species=("e", "i"))
+    Eo, Bo, Jo, sps = _oracle_steps(wl, 4)
+    run = GpuRun(wl, prec, kernel=pic.PIC_KERNEL_BATCHED, lane_stride=1, cell_order=4,
+                 chunk=8192, block=1024 if prec == pic.PIC_FP32_SPLIT else 512)
+    for k in range(4):
+        if k % 2 == 0:
+            run.sort()
+        run.particles()
+        pic.pic_fdtd_step(run.ctx, run.f)
+    run.check()
+    E, B, J = run.fields_np()
+    for a, b in ((E, Eo), (B, Bo), (J, Jo)):
+        assert rel_l2(a, b) <= tol and node_max_rel(a, b) <= tol, (rel_l2(a, b), node_max_rel(a, b))
+    _compare_state(run, sps, wl.boxes[0], tol, tol)
+    run.free()
+
+
+@pytest.mark.parametrize("prec,tol", ((pic.PIC_FP64, TOL64), (pic.PIC_FP32_SPLIT, TOL32)))
 @pytest.mark.parametrize("margin", (0, -1))
 def test_margin_on_some_axes(prec, tol, margin):
-    """Order-3 16x8x4 tiles: the staged margin does not fit on every axis,
-    so it is given up along x only; hot plasma drifts across tile faces in
-    every direction (LDS path inside the margin, global path beyond)."""
+    """Order-3 16x8x4 tiles with the staged margin where the LDS budget
+    holds it (margin 0) or without it (-1); hot plasma drifts across tile
+    faces in every direction (LDS path inside the margin, the global
+    straggler path beyond)."""
     wl = pi.uniform_box((32, 16, 12), 3, 0.05, 0.3, 3, 2300, "cpu", tile=(16, 8, 4),
                         fields="fourier", species=("e", "i"))
     Eo, Bo, Jo, sps = _oracle_steps(wl, 4)
