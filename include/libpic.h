@@ -234,7 +234,12 @@ pic_status pic_gather_push(pic_ctx *ctx, const pic_fields *f, pic_species *sp,
  * cyclically), J_x = -(q w dx / (dt dV)) times the running sum of W^x along
  * x, so that the discrete continuity equation d(rho)/dt + div J = 0 holds
  * to rounding.  Then positions are wrapped periodically.  J is FP64 in both
- * precisions, accumulated with atomics (order of the sum unspecified).
+ * precisions, accumulated with atomics (order of the sum unspecified).  In
+ * the tiled and batched split form each work item first sums its
+ * contributions in LDS as 64-bit fixed point (each FP32 contribution scaled
+ * by a power of two chosen from the item's largest |q w dx / (dt dV)| and
+ * truncated at 2^-30 of it; exact, order-independent sums), then adds them
+ * to J in FP64; a non-finite weight latches PIC_ERR_RANGE there.
  * PIC_ERR_STATE without a preceding pic_gather_push on the same species. */
 pic_status pic_deposit_J(pic_ctx *ctx, pic_fields *f, pic_species *sp,
                          int32_t nsp);
