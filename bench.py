@@ -439,6 +439,7 @@ def main():
     ap.add_argument("--sort-every", type=int, default=None)
     ap.add_argument("--cell-order", type=int, default=None)
     ap.add_argument("--stride", type=int, default=None, help="FP32 lane stride override")
+    ap.add_argument("--pad", type=int, default=None, help="FP32 LDS row padding override")
     ap.add_argument("--cell-order64", type=int, default=None)
     ap.add_argument("--stride64", type=int, default=None)
     ap.add_argument("--sort-every64", type=int, default=None)
@@ -469,6 +470,8 @@ def main():
         c32 = dataclasses.replace(c32, cell_order=args.cell_order)
     if args.stride is not None:
         c32 = dataclasses.replace(c32, lane_stride=args.stride)
+    if args.pad is not None:
+        c32 = dataclasses.replace(c32, pad=args.pad)
     if args.cell_order64 is not None:
         c64 = dataclasses.replace(c64, cell_order=args.cell_order64)
     if args.stride64 is not None:
