@@ -40,7 +40,55 @@ constexpr int O = PIC_ORDER;
 #endif
 using H = Halo<O>;
 
+// Largest field stage (bytes of dynamic LDS) copied with global -> LDS loads:
+// 64 KB less room for the kernel's static LDS, which lies below it.
+constexpr int LDS_DMA_LIMIT = 65536 - 1024;
+
 __device__ inline void flag_range(int *err) { atomicOr(err, 1); }
+
+// A workgroup-uniform descriptor (box, species) copied into scalar
+// registers, word by word.  Read through a reference instead, its fields
+// are reloaded with vector loads after every global store or atomic (the
+// compiler cannot rule out aliasing), and each reload waits for all of the
+// wave's stores and atomics in flight.
+template <class T>
+__device__ __forceinline__ T uniform_copy(const T &g) {
+    static_assert(sizeof(T) % 4 == 0, "descriptor of whole words");
+    int w[sizeof(T) / 4];
+    __builtin_memcpy(w, &g, sizeof(T));
+#pragma unroll
+    for (int k = 0; k < (int)(sizeof(T) / 4); ++k) w[k] = __builtin_amdgcn_readfirstlane(w[k]);
+    T r;
+    __builtin_memcpy(&r, w, sizeof(T));
+    return r;
+}
+
+// A pointer into device (global) memory that went through integer
+// registers, declared global again so that accesses through it compile to
+// global, not flat, memory instructions.
+template <class T>
+__device__ __forceinline__ T *global_ptr(T *p) {
+    return (T *)(__attribute__((address_space(1))) T *)(unsigned long long)p;
+}
+
+__device__ __forceinline__ DevSpecies uniform_species(const DevSpecies &g) {
+    DevSpecies s = uniform_copy(g);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        s.x[d] = global_ptr(s.x[d]);
+        s.off[d] = global_ptr(s.off[d]);
+        s.u[d] = global_ptr(s.u[d]);
+        s.xo[d] = global_ptr(s.xo[d]);
+        s.offo[d] = global_ptr(s.offo[d]);
+    }
+    s.cell = global_ptr(s.cell);
+    s.w = global_ptr(s.w);
+    s.cello = global_ptr(s.cello);
+    s.carry = global_ptr(s.carry);
+    s.strag = global_ptr(s.strag);
+    s.tile_off = global_ptr(s.tile_off);
+    return s;
+}
 
 // ------------------------------------------------------------ precision
 
@@ -50,13 +98,17 @@ struct F64 {
     using Acc = double;
     static constexpr int PREC = 0;
     static constexpr int MAX_BLOCK = 512;    // tiled kernels: threads per workgroup
-    // Old position from the species arrays or from scratch.
-    __device__ static bool load(const DevBox &b, double *const xs[3], long long i,
+    // Old position from the species arrays or from scratch (all words read
+    // before any is checked, so that the loads are in flight together).
+    __device__ __forceinline__ static bool load(const DevBox &b, double *const xs[3], long long i,
                                 int c[3], double f[3]) {
+        double xv[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) xv[d] = (b.dim == 2 && d == 1) ? 0.0 : xs[d][i];
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
             if (b.dim == 2 && d == 1) { c[d] = 0; f[d] = 0.0; continue; }
-            double x = xs[d][i];
+            double x = xv[d];
             if (!(x >= 0.0 && x < (double)b.n[d])) return false;
             double fl = floor(x);
             c[d] = (int)fl;
@@ -89,9 +141,13 @@ struct Split {
     using Acc = long long;
     static constexpr int PREC = 1;
     static constexpr int MAX_BLOCK = 1024;   // 128 VGPRs: 16 waves per CU
-    __device__ static bool load(const DevBox &b, const int *cells, float *const offs[3],
+    __device__ __forceinline__ static bool load(const DevBox &b, const int *cells, float *const offs[3],
                                 long long i, int c[3], float f[3]) {
-        int cell = cells[i];
+        // all words read before any is checked (loads in flight together)
+        const int cell = cells[i];
+        float ov[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) ov[d] = (b.dim == 2 && d == 1) ? 0.0f : offs[d][i];
         if (cell < 0 || (long long)cell >= b.ncells) return false;
         const int nx = b.n[0], nxy = b.n[0] * b.n[1];
         c[2] = div_exact(cell, nxy, b.inv_nxy);
@@ -101,7 +157,7 @@ struct Split {
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
             if (b.dim == 2 && d == 1) { f[d] = 0.0f; continue; }
-            float v = offs[d][i];
+            const float v = ov[d];
             if (!(v >= 0.0f && v < 1.0f)) return false;
             f[d] = v;
         }
@@ -935,8 +991,14 @@ __device__ __forceinline__ void particle_converged(const DevBox &b, const DevSpe
     using R = typename P::R;
     int c0[3], c1[3];
     R f0[3], f1[3], u[3] = {R(0), R(0), R(0)};
+    R wraw = R(0);
     bool valid = have;
     if (valid) {
+        // momentum and weight are read with the position, before any check,
+        // so that all of the slot's loads are in flight together
+        const R *ua[3] = {(const R *)sp.u[0], (const R *)sp.u[1], (const R *)sp.u[2]};
+        u[0] = ua[0][i]; u[1] = ua[1][i]; u[2] = ua[2][i];
+        wraw = ((const R *)sp.w)[i];
         bool ok;
         if constexpr (P::PREC == 0) ok = P::load(b, sp.x, i, c0, f0);
         else ok = P::load(b, sp.cell, sp.off, i, c0, f0);
@@ -948,10 +1010,7 @@ __device__ __forceinline__ void particle_converged(const DevBox &b, const DevSpe
     }
     if (!valid) {
 #pragma unroll
-        for (int d = 0; d < 3; ++d) { c0[d] = tile.t0[d]; f0[d] = R(0); }
-    } else {
-        const R *ua[3] = {(const R *)sp.u[0], (const R *)sp.u[1], (const R *)sp.u[2]};
-        u[0] = ua[0][i]; u[1] = ua[1][i]; u[2] = ua[2][i];
+        for (int d = 0; d < 3; ++d) { c0[d] = tile.t0[d]; f0[d] = R(0); u[d] = R(0); }
     }
     R E[3], B[3];
     gather<DIM, R>(lf, c0, f0, E, B, sp.galerkin);
@@ -988,7 +1047,7 @@ __device__ __forceinline__ void particle_converged(const DevBox &b, const DevSpe
             } else { c1[d] = c0[d]; f1[d] = fr; }
         }
     }
-    const R wgt = valid ? ((const R *)sp.w)[i] : R(0);
+    const R wgt = valid ? wraw : R(0);
     const double dV = b.dx[0] * b.dx[1] * b.dx[2];
     R cq[3];
 #pragma unroll
@@ -1054,8 +1113,8 @@ __global__ void __launch_bounds__(256) k_strag(KParams prm) {
     using JL = LdsJ<typename P::Acc>;
     const long long stride = (long long)gridDim.x * blockDim.x;
     for (int s = 0; s < prm.nsp; ++s) {
-        const DevSpecies &sp = prm.species[s];
-        const DevBox &b = prm.boxes[sp.box];
+        const DevSpecies sp = uniform_species(prm.species[s]);
+        const DevBox b = uniform_copy(prm.boxes[sp.box]);
         const long long n = prm.strag_count[s];
         for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride) {
             const long long i = sp.strag[k];
@@ -1108,7 +1167,7 @@ __device__ __forceinline__ void process_range(const KParams &prm, const DevBox &
                                               int p1, const Tile &tile,
                                               const LdsField<typename P::FieldT> &lf,
                                               const LdsJ<typename P::Acc> &lj) {
-    const DevSpecies &sp = prm.species[s];
+    const DevSpecies sp = uniform_species(prm.species[s]);
     // lane_swz: hardware lane bits 4 and 5 trade places (a bijection on each
     // wave's 64 slots; the block is a multiple of 64)
     const int hw = threadIdx.x;
@@ -1176,7 +1235,7 @@ __device__ __forceinline__ void process_item(const KParams &prm, const Item &it,
     using FT = typename P::FieldT;
     using A = typename P::Acc;
     const int box = item_box(prm, it);
-    const DevBox &b = prm.boxes[box];
+    const DevBox b = uniform_copy(prm.boxes[box]);
     Tile tile;
     {
         int t = it.t;
@@ -1242,18 +1301,45 @@ __device__ __forceinline__ void process_item(const KParams &prm, const Item &it,
 
     const int tid = threadIdx.x, bs = blockDim.x;
     if (MODE & MODE_PUSH) {
+        // The field stage is copied by global -> LDS loads (global_load_lds,
+        // one dword per lane into a wave's 64 consecutive LDS dwords at a
+        // wave-uniform base): no load result passes through a register, so
+        // a thread's loads all stay in flight until the wait before the
+        // barrier below.  FP64 values move as two dwords.  The LDS base of
+        // these loads travels in M0, whose LDS-address field is 16 bits wide
+        // on the parts with 64 KB of LDS; a stage that reaches past 64 KB
+        // (with the kernel's static LDS below it) takes the register copy.
+        constexpr int DW = (int)(sizeof(FT) / 4);
+        const int lane = tid & 63;
+        const bool dma = prm.lds_field_bytes <= LDS_DMA_LIMIT;
 #pragma unroll
         for (int c = 0; c < 6; ++c) {
-            FT *dst = (FT *)smem + lf.off[c];
-            const FT *src = (const FT *)(c < 3 ? prm.f.E[c] : prm.f.B[c - 3]);
-            const int n = lf.L01[c] * FL2[c];
-            RegionWalk w(tid, bs, lf.L0[c], FL1[c], FL2[c]);
-            for (int idx = tid; idx < n; idx += bs, w.next()) {
-                if (w.i >= W[c]) continue;
-                int gi = lf.o0[c] + w.i, gj = lf.o1[c] + w.j, gk = lf.o2[c] + w.k;
-                if (any) { gi = wrap_index_any(gi, b.n[0]); gj = wrap_index_any(gj, b.n[1]); gk = wrap_index_any(gk, b.n[2]); }
-                else { gi = wrap_index(gi, b.n[0]); gj = wrap_index(gj, b.n[1]); gk = wrap_index(gk, b.n[2]); }
-                dst[idx] = src[b.cell_base + gi + (long long)b.n[0] * (gj + (long long)b.n[1] * gk)];
+            const FT *srcf = (const FT *)(c < 3 ? prm.f.E[c] : prm.f.B[c - 3]);
+            if (dma) {
+                unsigned *dst = (unsigned *)((FT *)smem + lf.off[c]);
+                const unsigned *src = (const unsigned *)srcf;
+                const int nd = lf.L01[c] * FL2[c] * DW;
+                RegionWalk w(tid / DW, bs / DW, lf.L0[c], FL1[c], FL2[c]);
+                for (int id = tid; id < nd; id += bs, w.next()) {
+                    if (w.i >= W[c]) continue;
+                    int gi = lf.o0[c] + w.i, gj = lf.o1[c] + w.j, gk = lf.o2[c] + w.k;
+                    if (any) { gi = wrap_index_any(gi, b.n[0]); gj = wrap_index_any(gj, b.n[1]); gk = wrap_index_any(gk, b.n[2]); }
+                    else { gi = wrap_index(gi, b.n[0]); gj = wrap_index(gj, b.n[1]); gk = wrap_index(gk, b.n[2]); }
+                    const long long e = b.cell_base + gi + (long long)b.n[0] * (gj + (long long)b.n[1] * gk);
+                    __builtin_amdgcn_global_load_lds(src + e * DW + (DW > 1 ? (id & 1) : 0),
+                                                     dst + (id - lane), 4, 0, 0);
+                }
+            } else {
+                FT *dst = (FT *)smem + lf.off[c];
+                const int n = lf.L01[c] * FL2[c];
+                RegionWalk w(tid, bs, lf.L0[c], FL1[c], FL2[c]);
+                for (int idx = tid; idx < n; idx += bs, w.next()) {
+                    if (w.i >= W[c]) continue;
+                    int gi = lf.o0[c] + w.i, gj = lf.o1[c] + w.j, gk = lf.o2[c] + w.k;
+                    if (any) { gi = wrap_index_any(gi, b.n[0]); gj = wrap_index_any(gj, b.n[1]); gk = wrap_index_any(gk, b.n[2]); }
+                    else { gi = wrap_index(gi, b.n[0]); gj = wrap_index(gj, b.n[1]); gk = wrap_index(gk, b.n[2]); }
+                    dst[idx] = srcf[b.cell_base + gi + (long long)b.n[0] * (gj + (long long)b.n[1] * gk)];
+                }
             }
         }
     }
@@ -1280,10 +1366,16 @@ __device__ __forceinline__ void process_item(const KParams &prm, const Item &it,
             for (int d = 0; d < 3; ++d) qb = fmax(qb, fabs(sp.q * b.dx[d] / (b.dt * dV)));
             const float Q = (float)qb;
             const float *w = (const float *)sp.w;
-            for (int p = p0 + tid; p < p1; p += bs) {
-                const float x = fabsf(w[p]) * Q;
-                bad = bad || !(x <= 3.0e38f);
-                m = fmaxf(m, x);
+            // four loads in flight per thread
+            for (int p = p0 + tid; p < p1; p += 4 * bs) {
+                float x[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) x[u] = p + u * bs < p1 ? fabsf(w[p + u * bs]) * Q : 0.0f;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    bad = bad || !(x[u] <= 3.0e38f);
+                    m = fmaxf(m, x[u]);
+                }
             }
         };
         if (it.s >= 0) {
@@ -1300,6 +1392,8 @@ __device__ __forceinline__ void process_item(const KParams &prm, const Item &it,
         for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
         if ((tid & 63) == 0) red[tid >> 6] = m;
     }
+    // the global -> LDS copies of the field stage have landed
+    if (MODE & MODE_PUSH) __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if constexpr (FIXED) {
         float m = 0.0f;
@@ -1325,6 +1419,8 @@ __device__ __forceinline__ void process_item(const KParams &prm, const Item &it,
     __syncthreads();
     if (MODE & MODE_DEPOSIT) {
         const int n = 3 * lj.M012;
+        // component arrays selected in registers, not indexed in memory
+        double *const J0 = prm.f.J[0], *const J1 = prm.f.J[1], *const J2 = prm.f.J[2];
         RegionWalk w(tid, bs, lj.M0, lj.M1, M2);
         for (int idx = tid; idx < n; idx += bs, w.next()) {
             const A v = lj.base[idx];
@@ -1333,8 +1429,8 @@ __device__ __forceinline__ void process_item(const KParams &prm, const Item &it,
             int gi = lj.o0 + w.i, gj = lj.o1 + w.j, gk = lj.o2 + w.k;
             if (any) { gi = wrap_index_any(gi, b.n[0]); gj = wrap_index_any(gj, b.n[1]); gk = wrap_index_any(gk, b.n[2]); }
             else { gi = wrap_index(gi, b.n[0]); gj = wrap_index(gj, b.n[1]); gk = wrap_index(gk, b.n[2]); }
-            unsafeAtomicAdd(&prm.f.J[w.c][b.cell_base + gi + (long long)b.n[0] * (gj + (long long)b.n[1] * gk)],
-                            jv);
+            double *Jc = w.c == 0 ? J0 : w.c == 1 ? J1 : J2;
+            unsafeAtomicAdd(&Jc[b.cell_base + gi + (long long)b.n[0] * (gj + (long long)b.n[1] * gk)], jv);
         }
     }
     __syncthreads();
@@ -1355,7 +1451,11 @@ __global__ void __launch_bounds__(P::MAX_BLOCK) k_tiled(KParams prm) {
                 cur = idx < *prm.nitems ? prm.items[idx] : Item{0, -1, 0, 0};
             }
             __syncthreads();
-            it = cur;
+            // the item is the same for the whole workgroup
+            it.s = __builtin_amdgcn_readfirstlane(cur.s);
+            it.t = __builtin_amdgcn_readfirstlane(cur.t);
+            it.p0 = __builtin_amdgcn_readfirstlane(cur.p0);
+            it.p1 = __builtin_amdgcn_readfirstlane(cur.p1);
             __syncthreads();
             if (it.t < 0) return;
         } else {
