@@ -435,18 +435,30 @@ __global__ void k_permute_set(PermSet<T> ps, const int *perm, T *stage, long lon
     long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const long long j = perm[i];
+    // every load before any store: the compiler cannot tell that the stores
+    // leave the sources alone, and would otherwise wait for each load in turn
+    constexpr int G = PERM_GROUP_BYTES / (int)sizeof(T);
+    T v[G];
 #pragma unroll
-    for (int k = 0; k < PERM_GROUP_BYTES / (int)sizeof(T); ++k)
-        if (k < ps.n) stage[k * n + i] = ps.a[k][j];
+    for (int k = 0; k < G; ++k)
+        if (k < ps.n) v[k] = ps.a[k][j];
+#pragma unroll
+    for (int k = 0; k < G; ++k)
+        if (k < ps.n) stage[k * n + i] = v[k];
 }
 
 template <typename T>
 __global__ void k_unstage_set(PermSet<T> ps, const T *stage, long long n) {
     long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    constexpr int G = PERM_GROUP_BYTES / (int)sizeof(T);
+    T v[G];     // every load before any store (see k_permute_set)
 #pragma unroll
-    for (int k = 0; k < PERM_GROUP_BYTES / (int)sizeof(T); ++k)
-        if (k < ps.n) ps.a[k][i] = stage[k * n + i];
+    for (int k = 0; k < G; ++k)
+        if (k < ps.n) v[k] = stage[k * n + i];
+#pragma unroll
+    for (int k = 0; k < G; ++k)
+        if (k < ps.n) ps.a[k][i] = v[k];
 }
 
 
@@ -610,6 +622,9 @@ __global__ void k_faraday(DevFields f, const DevBox *boxes, const long long *fp,
     const T h = (T)(hfrac * b.dt);
     const T ix = (T)(1.0 / b.dx[0]), iy = (T)(1.0 / b.dx[1]), iz = (T)(1.0 / b.dx[2]);
     T ez = Ez[q.c], ey = Ey[q.c], ex = Ex[q.c];
+    // the cell's B read with E, before any store (which the compiler cannot
+    // tell apart from the sources, and would wait for load by load)
+    const T bx = Bx[q.c], by = By[q.c], bz = Bz[q.c];
     T dEz_dy = T(0), dEx_dy = T(0);
     if (b.dim == 3) { dEz_dy = (Ez[q.yp] - ez) * iy; dEx_dy = (Ex[q.yp] - ex) * iy; }
     T cx = dEz_dy - (Ey[q.zp] - ey) * iz;
@@ -621,14 +636,14 @@ __global__ void k_faraday(DevFields f, const DevBox *boxes, const long long *fp,
         double a1, b1, a0, b0;
         absorb_coef(absorb_sigma(b, k + 0.5), hh, a1, b1);
         absorb_coef(absorb_sigma(b, (double)k), hh, a0, b0);
-        Bx[q.c] = (T)a1 * Bx[q.c] - (T)b1 * cx;
-        By[q.c] = (T)a1 * By[q.c] - (T)b1 * cy;
-        Bz[q.c] = (T)a0 * Bz[q.c] - (T)b0 * cz;
+        Bx[q.c] = (T)a1 * bx - (T)b1 * cx;
+        By[q.c] = (T)a1 * by - (T)b1 * cy;
+        Bz[q.c] = (T)a0 * bz - (T)b0 * cz;
         return;
     }
-    Bx[q.c] -= h * cx;
-    By[q.c] -= h * cy;
-    Bz[q.c] -= h * cz;
+    Bx[q.c] = bx - h * cx;
+    By[q.c] = by - h * cy;
+    Bz[q.c] = bz - h * cz;
 }
 
 // E += dt (curl B - J), curl B at the E points.
@@ -645,6 +660,9 @@ __global__ void k_ampere(DevFields f, const DevBox *boxes, const long long *fp, 
     const T dt = (T)b.dt;
     const T ix = (T)(1.0 / b.dx[0]), iy = (T)(1.0 / b.dx[1]), iz = (T)(1.0 / b.dx[2]);
     T bx = Bx[q.c], by = By[q.c], bz = Bz[q.c];
+    // the cell's E and J read before any store (see k_faraday)
+    const T ex = Ex[q.c], ey = Ey[q.c], ez = Ez[q.c];
+    const T jx = (T)f.J[0][q.c], jy = (T)f.J[1][q.c], jz = (T)f.J[2][q.c];
     T dBz_dy = T(0), dBx_dy = T(0);
     if (b.dim == 3) { dBz_dy = (bz - Bz[q.ym]) * iy; dBx_dy = (bx - Bx[q.ym]) * iy; }
     T cx = dBz_dy - (by - By[q.zm]) * iz;
@@ -656,14 +674,14 @@ __global__ void k_ampere(DevFields f, const DevBox *boxes, const long long *fp, 
         double a0, b0, a1, b1;
         absorb_coef(absorb_sigma(b, (double)k), b.dt, a0, b0);
         absorb_coef(absorb_sigma(b, k + 0.5), b.dt, a1, b1);
-        Ex[q.c] = (T)a0 * Ex[q.c] + (T)b0 * (cx - (T)f.J[0][q.c]);
-        Ey[q.c] = (T)a0 * Ey[q.c] + (T)b0 * (cy - (T)f.J[1][q.c]);
-        Ez[q.c] = (T)a1 * Ez[q.c] + (T)b1 * (cz - (T)f.J[2][q.c]);
+        Ex[q.c] = (T)a0 * ex + (T)b0 * (cx - jx);
+        Ey[q.c] = (T)a0 * ey + (T)b0 * (cy - jy);
+        Ez[q.c] = (T)a1 * ez + (T)b1 * (cz - jz);
         return;
     }
-    Ex[q.c] += dt * (cx - (T)f.J[0][q.c]);
-    Ey[q.c] += dt * (cy - (T)f.J[1][q.c]);
-    Ez[q.c] += dt * (cz - (T)f.J[2][q.c]);
+    Ex[q.c] = ex + dt * (cx - jx);
+    Ey[q.c] = ey + dt * (cy - jy);
+    Ez[q.c] = ez + dt * (cz - jz);
 }
 
 // Node divergence of an E-staggered vector field (FP64).
