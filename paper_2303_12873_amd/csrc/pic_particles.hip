@@ -43,6 +43,9 @@ using H = Halo<O>;
 // Largest field stage (bytes of dynamic LDS) copied with global -> LDS loads:
 // 64 KB less room for the kernel's static LDS, which lies below it.
 constexpr int LDS_DMA_LIMIT = 65536 - 1024;
+// Field values a thread loads before storing them to LDS when the stage is
+// copied through registers.
+constexpr int STAGE_BATCH = 4;
 
 __device__ inline void flag_range(int *err) { atomicOr(err, 1); }
 
@@ -1330,15 +1333,31 @@ __device__ __forceinline__ void process_item(const KParams &prm, const Item &it,
                                                      dst + (id - lane), 4, 0, 0);
                 }
             } else {
+                // through registers: STAGE_BATCH loads in flight per thread
+                // before their LDS stores (one at a time, each store waits
+                // for its load's full latency)
                 FT *dst = (FT *)smem + lf.off[c];
                 const int n = lf.L01[c] * FL2[c];
                 RegionWalk w(tid, bs, lf.L0[c], FL1[c], FL2[c]);
-                for (int idx = tid; idx < n; idx += bs, w.next()) {
-                    if (w.i >= W[c]) continue;
-                    int gi = lf.o0[c] + w.i, gj = lf.o1[c] + w.j, gk = lf.o2[c] + w.k;
-                    if (any) { gi = wrap_index_any(gi, b.n[0]); gj = wrap_index_any(gj, b.n[1]); gk = wrap_index_any(gk, b.n[2]); }
-                    else { gi = wrap_index(gi, b.n[0]); gj = wrap_index(gj, b.n[1]); gk = wrap_index(gk, b.n[2]); }
-                    dst[idx] = srcf[b.cell_base + gi + (long long)b.n[0] * (gj + (long long)b.n[1] * gk)];
+                for (int idx0 = tid; idx0 < n; idx0 += STAGE_BATCH * bs) {
+                    const FT *src[STAGE_BATCH];
+                    bool ok[STAGE_BATCH];
+#pragma unroll
+                    for (int u = 0; u < STAGE_BATCH; ++u) {
+                        // addresses first (only those of staged entries are read)
+                        ok[u] = idx0 + u * bs < n && w.i < W[c];
+                        int gi = lf.o0[c] + w.i, gj = lf.o1[c] + w.j, gk = lf.o2[c] + w.k;
+                        if (any) { gi = wrap_index_any(gi, b.n[0]); gj = wrap_index_any(gj, b.n[1]); gk = wrap_index_any(gk, b.n[2]); }
+                        else { gi = wrap_index(gi, b.n[0]); gj = wrap_index(gj, b.n[1]); gk = wrap_index(gk, b.n[2]); }
+                        src[u] = srcf + b.cell_base + gi + (long long)b.n[0] * (gj + (long long)b.n[1] * gk);
+                        w.next();
+                    }
+                    FT v[STAGE_BATCH];
+#pragma unroll
+                    for (int u = 0; u < STAGE_BATCH; ++u) v[u] = ok[u] ? *src[u] : FT(0);
+#pragma unroll
+                    for (int u = 0; u < STAGE_BATCH; ++u)
+                        if (ok[u]) dst[idx0 + u * bs] = v[u];
                 }
             }
         }
