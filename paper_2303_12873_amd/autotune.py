@@ -46,12 +46,13 @@ class Candidate:
 # The configurations the autotuner picks on the 256x256x2048 two-species
 # order-3 laser-plasma box: FP32 split batched (16x8x4 tiles, 1024 threads,
 # lane stride 1 over the rank-major order, sort every 16 steps) and FP64
-# plain tiled (16x8x4 tiles, 512 threads, lane stride 4, sort every 4
+# plain tiled (8x8x8 tiles, 512 threads, lane stride 4, sort every 4
 # steps: its larger LDS stage leaves less room for the staged margin, so
-# its stragglers grow faster between sorts).  bench.py times these unless
-# asked to tune, and the full-size parity tests run exactly them.
+# its stragglers grow faster between sorts; 16x8x4 tiles run within 1% of
+# it).  bench.py times these unless asked to tune, and the full-size
+# parity tests run exactly them.
 PICK_FP32 = Candidate((16, 8, 4), 1024, 8192, 2, 1, 4, 16, 0, 0)
-PICK_FP64 = Candidate((16, 8, 4), 512, 8192, 2, 4, -1, 4, 0, 0)
+PICK_FP64 = Candidate((8, 8, 8), 512, 8192, 2, 4, -1, 4, 0, 0)
 
 
 def default_space(dim3: bool, precision=pic.PIC_FP32_SPLIT, sort_every=(4, 8, 16)):
