@@ -288,7 +288,9 @@ __device__ __forceinline__ R interp(const FA &fa, int comp, const GWin<O, R> &wx
         return sum;
     }
     if (DIM == 3) {
-#pragma unroll
+        // from global memory one plane at a time: with every plane's loads
+        // hoisted together the straggler kernels ran out of registers
+#pragma unroll 1
         for (int kk = 0; kk <= O; ++kk) {
             R sy = R(0);
 #pragma unroll
@@ -299,7 +301,12 @@ __device__ __forceinline__ R interp(const FA &fa, int comp, const GWin<O, R> &wx
                     sx += wx.w[ii] * (R)fa.load(comp, wx.base + ii, wy.base + jj, wz.base + kk);
                 sy += wy.w[jj] * sx;
             }
-            sum += wz.w[kk] * sy;
+            // the plane's weight by selects: indexing the window with the
+            // loop counter would put it in scratch memory
+            R wk = wz.w[0];
+#pragma unroll
+            for (int m = 1; m <= O; ++m) wk = kk == m ? wz.w[m] : wk;
+            sum += wk * sy;
         }
     } else {
 #pragma unroll
