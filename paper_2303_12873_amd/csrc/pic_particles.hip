@@ -40,11 +40,8 @@ constexpr int O = PIC_ORDER;
 #endif
 using H = Halo<O>;
 
-// Largest field stage (bytes of dynamic LDS) copied with global -> LDS loads:
-// 64 KB less room for the kernel's static LDS, which lies below it.
-constexpr int LDS_DMA_LIMIT = 65536 - 1024;
-// Field values a thread loads before storing them to LDS when the stage is
-// copied through registers.
+// FP64 field values a thread loads before storing them to LDS (the FP64
+// stage is copied through registers).
 constexpr int STAGE_BATCH = 4;
 
 __device__ inline void flag_range(int *err) { atomicOr(err, 1); }
@@ -1311,33 +1308,30 @@ __device__ __forceinline__ void process_item(const KParams &prm, const Item &it,
 
     const int tid = threadIdx.x, bs = blockDim.x;
     if (MODE & MODE_PUSH) {
-        // The field stage is copied by global -> LDS loads (global_load_lds,
-        // one dword per lane into a wave's 64 consecutive LDS dwords at a
-        // wave-uniform base): no load result passes through a register, so
-        // a thread's loads all stay in flight until the wait before the
-        // barrier below.  FP64 values move as two dwords.  The LDS base of
-        // these loads travels in M0, whose LDS-address field is 16 bits wide
-        // on the parts with 64 KB of LDS; a stage that reaches past 64 KB
-        // (with the kernel's static LDS below it) takes the register copy.
-        constexpr int DW = (int)(sizeof(FT) / 4);
+        // FP32 stage: global -> LDS loads (global_load_lds_dword, one dword
+        // per lane into a wave's 64 consecutive LDS words at a wave-uniform
+        // base held in M0, which on gfx950 reaches the whole LDS, past 64 KB
+        // too): no value passes through a register, so a thread's loads all
+        // stay in flight until the wait before the barrier below.  FP64
+        // stage: through registers, STAGE_BATCH 8-byte loads in flight per
+        // thread (faster for FP64 than two dword copies per value).
         const int lane = tid & 63;
-        const bool dma = prm.lds_field_bytes <= LDS_DMA_LIMIT;
+        constexpr bool dma = sizeof(FT) == 4;
 #pragma unroll
         for (int c = 0; c < 6; ++c) {
             const FT *srcf = (const FT *)(c < 3 ? prm.f.E[c] : prm.f.B[c - 3]);
-            if (dma) {
+            if constexpr (dma) {
                 unsigned *dst = (unsigned *)((FT *)smem + lf.off[c]);
                 const unsigned *src = (const unsigned *)srcf;
-                const int nd = lf.L01[c] * FL2[c] * DW;
-                RegionWalk w(tid / DW, bs / DW, lf.L0[c], FL1[c], FL2[c]);
+                const int nd = lf.L01[c] * FL2[c];
+                RegionWalk w(tid, bs, lf.L0[c], FL1[c], FL2[c]);
                 for (int id = tid; id < nd; id += bs, w.next()) {
                     if (w.i >= W[c]) continue;
                     int gi = lf.o0[c] + w.i, gj = lf.o1[c] + w.j, gk = lf.o2[c] + w.k;
                     if (any) { gi = wrap_index_any(gi, b.n[0]); gj = wrap_index_any(gj, b.n[1]); gk = wrap_index_any(gk, b.n[2]); }
                     else { gi = wrap_index(gi, b.n[0]); gj = wrap_index(gj, b.n[1]); gk = wrap_index(gk, b.n[2]); }
                     const long long e = b.cell_base + gi + (long long)b.n[0] * (gj + (long long)b.n[1] * gk);
-                    __builtin_amdgcn_global_load_lds(src + e * DW + (DW > 1 ? (id & 1) : 0),
-                                                     dst + (id - lane), 4, 0, 0);
+                    __builtin_amdgcn_global_load_lds(src + e, dst + (id - lane), 4, 0, 0);
                 }
             } else {
                 // through registers: STAGE_BATCH loads in flight per thread

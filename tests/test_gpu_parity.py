@@ -559,7 +559,9 @@ def test_rank_major_lane_stride_1_with_resorts(prec, tol):
     """The split form's launch configuration on the 256x256x2048 box (16x8x4
     tiles, 1024 threads, lane stride 1 over the rank-major order, chunk
     8192) on a small two-species box: four steps with a re-sort before the
-    first and the third, fields and particles against the oracle."""
+    first and the third, fields and particles against the oracle.  Its FP32
+    field stage (66 KB with the 1-cell margin) is copied by global -> LDS
+    loads that land partly past 64 KB of LDS."""
     wl = pi.uniform_box((32, 16, 12), 4, 0.05, 0.3, 3, 2500, "cpu", tile=(16, 8, 4),
                         fields="fourier", species=("e", "i"))
     Eo, Bo, Jo, sps = _oracle_steps(wl, 4)
