@@ -107,6 +107,7 @@ struct pic_ctx {
     int margin[3] = {0, 0, 0};      // cells staged around each tile, per axis
     int jrow = 0;                   // padded row length of the LDS current tile (0 = none)
     int frow = 0;                   // padded row length of the LDS field tile (0 = none)
+    int falign = 0;                 // field rows aligned to 4 nodes (16-byte copies)
     int lane_swz = 0;               // swap lane bits 4 and 5 (16-wide rows, padded FP32 field)
     // species
     std::vector<Slot> slots;
@@ -450,6 +451,7 @@ KParams make_params(pic_ctx *c, const pic_fields *f, int nsp) {
     for (int d = 0; d < 3; ++d) k.margin[d] = c->margin[d];
     k.jrow = c->jrow;
     k.frow = c->frow;
+    k.falign = c->falign;
     k.lane_swz = c->lane_swz;
     k.strag_count = c->strag_count;
     k.box_sp_off = c->dbox_sp_off;
@@ -1253,6 +1255,15 @@ pic_status pic_init(pic_ctx **out, const pic_box_desc *boxes, int32_t nboxes, pi
     // LDS bytes of the field (F) or current (J) stage for a margin per axis
     // and a padded row length (0 = unpadded), max over the boxes.
     // (each field component spans only its own stencil's nodes, by stagger)
+    // FP32 field rows from and to multiples of 4 nodes, so that the stage
+    // is copied 16 bytes a lane: every box's x tile and x size a multiple
+    // of 4 cells and its first cell at a multiple of 4 in the arrays; the
+    // rows are not padded further.
+    bool falign_ok = fb == 4 && t.pad == 0;
+    for (int i = 0; i < nboxes; ++i)
+        falign_ok = falign_ok && boxes[i].tile[0] % 4 == 0 && boxes[i].n[0] % 4 == 0 &&
+                    boxes[i].cell_base % 4 == 0;
+    bool falign = falign_ok;
     auto stage_bytes = [&](bool field, const int *mg, int row) {
         size_t mx = 0;
         for (int i = 0; i < nboxes; ++i) {
@@ -1266,7 +1277,12 @@ pic_status pic_init(pic_ctx **out, const pic_box_desc *boxes, int32_t nboxes, pi
                     const int lo = field ? gather_lo(o, st) : halo_jl(o);
                     const int hi = field ? gather_hi(o, st) : halo_jh(o);
                     size_t w = (size_t)(std::min(b.tile[k], b.n[k]) + lo + hi + 2 * mg[k]);
+                    if (field && k == 0 && falign)   // [t0 - lo, t0 + te + hi) to multiples of 4
+                        w = (size_t)(((std::min(b.tile[k], b.n[k]) + hi + mg[k] + 3) & ~3) +
+                                     ((lo + mg[k] + 3) & ~3));
                     if (k == 0 && row > 0) w = std::max(w, (size_t)row);
+                    // J_z's edges along z end one node before the region
+                    if (!field && c == 2 && k == 2) w -= 1;
                     n *= w;
                 }
                 by += n;
@@ -1293,6 +1309,8 @@ pic_status pic_init(pic_ctx **out, const pic_box_desc *boxes, int32_t nboxes, pi
         std::stable_sort(drop, drop + 3, [&](int a, int b) { return ext[a] > ext[b]; });
         const int m0 = t.margin < 0 ? 0 : 1;
         int mg[3] = {m0, m0, m0};
+        // aligned rows only where they fit with the full margin
+        if (falign && layout(mg, false, false, fr, jr) > cap) falign = false;
         for (int i = 0; i < 3 && layout(mg, false, false, fr, jr) > cap; ++i) mg[drop[i]] = 0;
         bool padf = false, padj = false;
         if (t.pad >= 0) {
@@ -1319,6 +1337,7 @@ pic_status pic_init(pic_ctx **out, const pic_box_desc *boxes, int32_t nboxes, pi
         c->frow = fr;
         c->jrow = jr;
         c->lane_swz = tx == 16 && fb == 4 && fr > 0;
+        c->falign = falign && fr == 0;
         for (int k = 0; k < 3; ++k) c->margin[k] = mg[k];
         c->lds_field_bytes = stage_bytes(true, mg, fr);
     }

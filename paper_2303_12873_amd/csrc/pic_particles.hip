@@ -235,7 +235,10 @@ template <typename A> struct LdsJ {
     static constexpr bool LDS = true;
     static constexpr bool FIXED = std::is_integral<A>::value;
     A *base;
-    int o0, o1, o2, M0, M1, M012;
+    // components c = 0, 1, 2 at base + c * M012, rows of M0, M1 rows per
+    // plane; N entries in all: J_z, whose edges along z end one node before
+    // the region does, goes without its last plane
+    int o0, o1, o2, M0, M1, M012, N;
     // fixed point: contributions are scaled by `scale` = 2^s before the
     // integer add, and the flush multiplies by `unscale` = 2^-s
     float scale;
@@ -1285,7 +1288,13 @@ __device__ __forceinline__ void process_item(const KParams &prm, const Item &it,
             }
             W[c] = w[0];
             lf.o0[c] = tile.t0[0] - lo[0];
-            lf.L0[c] = max(w[0], prm.frow);
+            if (prm.falign) {
+                // rows from and to multiples of 4 nodes (16-byte copies)
+                const int a0 = lf.o0[c] & ~3;
+                W[c] = ((lf.o0[c] + w[0] + 3) & ~3) - a0;
+                lf.o0[c] = a0;
+            }
+            lf.L0[c] = max(W[c], prm.frow);
             lf.o2[c] = tile.t0[2] - lo[2];
             FL2[c] = w[2];
             if (DIM == 3) { lf.o1[c] = tile.t0[1] - lo[1]; FL1[c] = w[1]; }
@@ -1305,6 +1314,7 @@ __device__ __forceinline__ void process_item(const KParams &prm, const Item &it,
     if (DIM == 3) { lj.o1 = tile.t0[1] - JL[1]; lj.M1 = tile.te[1] + JW[1]; }
     else { lj.o1 = 0; lj.M1 = 1; }
     lj.M012 = lj.M0 * lj.M1 * M2;
+    lj.N = 3 * lj.M012 - lj.M0 * lj.M1;
 
     const int tid = threadIdx.x, bs = blockDim.x;
     if (MODE & MODE_PUSH) {
@@ -1323,15 +1333,34 @@ __device__ __forceinline__ void process_item(const KParams &prm, const Item &it,
             if constexpr (dma) {
                 unsigned *dst = (unsigned *)((FT *)smem + lf.off[c]);
                 const unsigned *src = (const unsigned *)srcf;
-                const int nd = lf.L01[c] * FL2[c];
-                RegionWalk w(tid, bs, lf.L0[c], FL1[c], FL2[c]);
-                for (int id = tid; id < nd; id += bs, w.next()) {
-                    if (w.i >= W[c]) continue;
-                    int gi = lf.o0[c] + w.i, gj = lf.o1[c] + w.j, gk = lf.o2[c] + w.k;
-                    if (any) { gi = wrap_index_any(gi, b.n[0]); gj = wrap_index_any(gj, b.n[1]); gk = wrap_index_any(gk, b.n[2]); }
-                    else { gi = wrap_index(gi, b.n[0]); gj = wrap_index(gj, b.n[1]); gk = wrap_index(gk, b.n[2]); }
-                    const long long e = b.cell_base + gi + (long long)b.n[0] * (gj + (long long)b.n[1] * gk);
-                    __builtin_amdgcn_global_load_lds(src + e, dst + (id - lane), 4, 0, 0);
+                // 16 bytes a lane: aligned, unpadded rows that need no wrap
+                // along x, from a 16-byte aligned array and first cell
+                const bool x4 = prm.falign && lf.L0[c] == W[c] && lf.o0[c] >= 0 &&
+                                lf.o0[c] + W[c] <= b.n[0] && (b.n[0] & 3) == 0 &&
+                                (b.cell_base & 3) == 0 && ((unsigned long long)srcf & 15) == 0;
+                if (x4) {
+                    const int q = W[c] >> 2;    // 4-node chunks per row
+                    const int nq = q * FL1[c] * FL2[c];
+                    RegionWalk w(tid, bs, q, FL1[c], FL2[c]);
+                    for (int id = tid; id < nq; id += bs, w.next()) {
+                        int gj = lf.o1[c] + w.j, gk = lf.o2[c] + w.k;
+                        if (any) { gj = wrap_index_any(gj, b.n[1]); gk = wrap_index_any(gk, b.n[2]); }
+                        else { gj = wrap_index(gj, b.n[1]); gk = wrap_index(gk, b.n[2]); }
+                        const long long e = b.cell_base + lf.o0[c] + 4 * w.i +
+                                            (long long)b.n[0] * (gj + (long long)b.n[1] * gk);
+                        __builtin_amdgcn_global_load_lds(src + e, dst + 4 * (id - lane), 16, 0, 0);
+                    }
+                } else {
+                    const int nd = lf.L01[c] * FL2[c];
+                    RegionWalk w(tid, bs, lf.L0[c], FL1[c], FL2[c]);
+                    for (int id = tid; id < nd; id += bs, w.next()) {
+                        if (w.i >= W[c]) continue;
+                        int gi = lf.o0[c] + w.i, gj = lf.o1[c] + w.j, gk = lf.o2[c] + w.k;
+                        if (any) { gi = wrap_index_any(gi, b.n[0]); gj = wrap_index_any(gj, b.n[1]); gk = wrap_index_any(gk, b.n[2]); }
+                        else { gi = wrap_index(gi, b.n[0]); gj = wrap_index(gj, b.n[1]); gk = wrap_index(gk, b.n[2]); }
+                        const long long e = b.cell_base + gi + (long long)b.n[0] * (gj + (long long)b.n[1] * gk);
+                        __builtin_amdgcn_global_load_lds(src + e, dst + (id - lane), 4, 0, 0);
+                    }
                 }
             } else {
                 // through registers: STAGE_BATCH loads in flight per thread
@@ -1364,7 +1393,7 @@ __device__ __forceinline__ void process_item(const KParams &prm, const Item &it,
         }
     }
     if (MODE & MODE_DEPOSIT) {
-        const int n = 3 * lj.M012;
+        const int n = lj.N;
         for (int idx = tid; idx < n; idx += bs) lj.base[idx] = A(0);
     }
     constexpr bool FIXED = LdsJ<A>::FIXED && (MODE & MODE_DEPOSIT);
@@ -1438,7 +1467,7 @@ __device__ __forceinline__ void process_item(const KParams &prm, const Item &it,
     }
     __syncthreads();
     if (MODE & MODE_DEPOSIT) {
-        const int n = 3 * lj.M012;
+        const int n = lj.N;
         // component arrays selected in registers, not indexed in memory
         double *const J0 = prm.f.J[0], *const J1 = prm.f.J[1], *const J2 = prm.f.J[2];
         RegionWalk w(tid, bs, lj.M0, lj.M1, M2);
