@@ -580,6 +580,29 @@ def test_rank_major_lane_stride_1_with_resorts(prec, tol):
     run.free()
 
 
+def test_aligned_field_rows_interior_tiles():
+    """The split form's FP32 field rows aligned to 4 nodes and copied 16
+    bytes a lane: on a 48-wide box the middle 16x8x4 tiles stage rows that
+    need no wrap along x (the 16-byte copy), the edge tiles wrap (the dword
+    copy into the same aligned rows); three steps against the oracle, node
+    by node, and the particles."""
+    wl = pi.uniform_box((48, 16, 12), 4, 0.05, 0.3, 3, 2600, "cpu", tile=(16, 8, 4),
+                        fields="fourier", species=("e", "i"))
+    Eo, Bo, Jo, sps = _oracle_steps(wl, 3)
+    run = GpuRun(wl, pic.PIC_FP32_SPLIT, kernel=pic.PIC_KERNEL_BATCHED, lane_stride=1,
+                 cell_order=4, chunk=8192, block=1024)
+    run.sort()
+    for _ in range(3):
+        run.particles()
+        pic.pic_fdtd_step(run.ctx, run.f)
+    run.check()
+    E, B, J = run.fields_np()
+    for a, b in ((E, Eo), (B, Bo), (J, Jo)):
+        assert rel_l2(a, b) <= TOL32 and node_max_rel(a, b) <= TOL32, (rel_l2(a, b), node_max_rel(a, b))
+    _compare_state(run, sps, wl.boxes[0], TOL32, TOL32)
+    run.free()
+
+
 @pytest.mark.parametrize("prec,tol", ((pic.PIC_FP64, TOL64), (pic.PIC_FP32_SPLIT, TOL32)))
 @pytest.mark.parametrize("margin", (0, -1))
 def test_margin_on_some_axes(prec, tol, margin):
