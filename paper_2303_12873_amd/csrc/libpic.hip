@@ -1336,8 +1336,10 @@ pic_status pic_init(pic_ctx **out, const pic_box_desc *boxes, int32_t nboxes, pi
         c->lds_bytes = layout(mg, padf, padj, fr, jr);
         c->frow = fr;
         c->jrow = jr;
-        c->lane_swz = tx == 16 && fb == 4 && fr > 0;
         c->falign = falign && fr == 0;
+        // FP32 rows of 24 (padded, or aligned to 4 nodes around a 16-wide
+        // tile): a half-wave on rows r and r + 2 of a pass is conflict-free
+        c->lane_swz = tx == 16 && fb == 4 && (fr > 0 || c->falign);
         for (int k = 0; k < 3; ++k) c->margin[k] = mg[k];
         c->lds_field_bytes = stage_bytes(true, mg, fr);
     }
