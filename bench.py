@@ -57,7 +57,8 @@ PEAK_HBM_GBS = 8000.0
 # instructions (the kernels are built without them) and for FP64.
 PEAK_VALU_TFLOPS = 78.6
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_tiled_split_c5_traffic.md")
-KERNEL_SOURCES = ("pic_particles.hip", "pic_math.h", "pic_dev.h")
+# the particle kernel and the host code that lays out its LDS tiles
+KERNEL_SOURCES = ("pic_particles.hip", "pic_math.h", "pic_dev.h", "libpic.hip")
 
 
 def kernel_source_sha():
