@@ -107,7 +107,7 @@ struct pic_ctx {
     int margin[3] = {0, 0, 0};      // cells staged around each tile, per axis
     int jrow = 0;                   // padded row length of the LDS current tile (0 = none)
     int frow = 0;                   // padded row length of the LDS field tile (0 = none)
-    int falign = 0;                 // field rows aligned to 4 nodes (16-byte copies)
+    int falign = 0;                 // field rows aligned to 16 bytes (16-byte copies)
     int lane_swz = 0;               // swap lane bits 4 and 5 (16-wide rows, padded FP32 field)
     // species
     std::vector<Slot> slots;
@@ -1255,14 +1255,15 @@ pic_status pic_init(pic_ctx **out, const pic_box_desc *boxes, int32_t nboxes, pi
     // LDS bytes of the field (F) or current (J) stage for a margin per axis
     // and a padded row length (0 = unpadded), max over the boxes.
     // (each field component spans only its own stencil's nodes, by stagger)
-    // FP32 field rows from and to multiples of 4 nodes, so that the stage
-    // is copied 16 bytes a lane: every box's x tile and x size a multiple
-    // of 4 cells and its first cell at a multiple of 4 in the arrays; the
-    // rows are not padded further.
-    bool falign_ok = fb == 4 && t.pad == 0;
+    // Field rows from and to multiples of 16 bytes (al = 4 FP32 or 2 FP64
+    // nodes), so that the stage is copied 16 bytes a lane: every box's x
+    // tile and x size a multiple of al cells and its first cell at a
+    // multiple of al in the arrays; the rows are not padded further.
+    const int al = 16 / fb;
+    bool falign_ok = t.pad == 0;
     for (int i = 0; i < nboxes; ++i)
-        falign_ok = falign_ok && boxes[i].tile[0] % 4 == 0 && boxes[i].n[0] % 4 == 0 &&
-                    boxes[i].cell_base % 4 == 0;
+        falign_ok = falign_ok && boxes[i].tile[0] % al == 0 && boxes[i].n[0] % al == 0 &&
+                    boxes[i].cell_base % al == 0;
     bool falign = falign_ok;
     auto stage_bytes = [&](bool field, const int *mg, int row) {
         size_t mx = 0;
@@ -1277,9 +1278,9 @@ pic_status pic_init(pic_ctx **out, const pic_box_desc *boxes, int32_t nboxes, pi
                     const int lo = field ? gather_lo(o, st) : halo_jl(o);
                     const int hi = field ? gather_hi(o, st) : halo_jh(o);
                     size_t w = (size_t)(std::min(b.tile[k], b.n[k]) + lo + hi + 2 * mg[k]);
-                    if (field && k == 0 && falign)   // [t0 - lo, t0 + te + hi) to multiples of 4
-                        w = (size_t)(((std::min(b.tile[k], b.n[k]) + hi + mg[k] + 3) & ~3) +
-                                     ((lo + mg[k] + 3) & ~3));
+                    if (field && k == 0 && falign)   // [t0 - lo, t0 + te + hi) to multiples of al
+                        w = (size_t)(((std::min(b.tile[k], b.n[k]) + hi + mg[k] + al - 1) & -al) +
+                                     ((lo + mg[k] + al - 1) & -al));
                     if (k == 0 && row > 0) w = std::max(w, (size_t)row);
                     // J_z's edges along z end one node before the region
                     if (!field && c == 2 && k == 2) w -= 1;
@@ -1309,9 +1310,15 @@ pic_status pic_init(pic_ctx **out, const pic_box_desc *boxes, int32_t nboxes, pi
         std::stable_sort(drop, drop + 3, [&](int a, int b) { return ext[a] > ext[b]; });
         const int m0 = t.margin < 0 ? 0 : 1;
         int mg[3] = {m0, m0, m0};
-        // aligned rows only where they fit with the full margin
-        if (falign && layout(mg, false, false, fr, jr) > cap) falign = false;
+        // FP32: aligned rows only where they fit with the full margin.
+        // FP64 (whose stage rarely holds the margin): the margin axes are
+        // given up first without them, then aligned rows where they fit.
+        if (falign && (fb == 8 || layout(mg, false, false, fr, jr) > cap)) falign = false;
         for (int i = 0; i < 3 && layout(mg, false, false, fr, jr) > cap; ++i) mg[drop[i]] = 0;
+        if (falign_ok && fb == 8) {
+            falign = true;
+            if (layout(mg, false, false, fr, jr) > cap) falign = false;
+        }
         bool padf = false, padj = false;
         if (t.pad >= 0) {
             // pad 0: current rows; 1: field rows, then current rows, each

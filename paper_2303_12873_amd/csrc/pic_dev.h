@@ -91,8 +91,8 @@ struct KParams {
     int margin[3];            // cells staged around each tile per axis (0 or 1)
     int jrow;                 // minimum row length of the LDS current tile
     int frow;                 // minimum row length of the LDS field tile
-    int falign;               // 1: field rows from and to multiples of 4
-                              // nodes (FP32 stage copied 16 bytes a lane)
+    int falign;               // 1: field rows from and to multiples of 16
+                              // bytes (stage copied 16 bytes a lane)
     int lane_swz;             // 1: slots of a wave swap lane bits 4 and 5, so
                               // that with 16-wide tile rows the 32 lanes of
                               // one LDS pass of a 4-byte field read hold

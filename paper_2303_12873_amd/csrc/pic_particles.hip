@@ -1289,9 +1289,11 @@ __device__ __forceinline__ void process_item(const KParams &prm, const Item &it,
             W[c] = w[0];
             lf.o0[c] = tile.t0[0] - lo[0];
             if (prm.falign) {
-                // rows from and to multiples of 4 nodes (16-byte copies)
-                const int a0 = lf.o0[c] & ~3;
-                W[c] = ((lf.o0[c] + w[0] + 3) & ~3) - a0;
+                // rows from and to multiples of 16 bytes (4 FP32 or 2 FP64
+                // nodes: 16-byte copies)
+                constexpr int AL = 16 / (int)sizeof(FT);
+                const int a0 = lf.o0[c] & ~(AL - 1);
+                W[c] = ((lf.o0[c] + w[0] + AL - 1) & ~(AL - 1)) - a0;
                 lf.o0[c] = a0;
             }
             lf.L0[c] = max(W[c], prm.frow);
@@ -1318,49 +1320,51 @@ __device__ __forceinline__ void process_item(const KParams &prm, const Item &it,
 
     const int tid = threadIdx.x, bs = blockDim.x;
     if (MODE & MODE_PUSH) {
-        // FP32 stage: global -> LDS loads (global_load_lds_dword, one dword
-        // per lane into a wave's 64 consecutive LDS words at a wave-uniform
-        // base held in M0, which on gfx950 reaches the whole LDS, past 64 KB
-        // too): no value passes through a register, so a thread's loads all
-        // stay in flight until the wait before the barrier below.  FP64
-        // stage: through registers, STAGE_BATCH 8-byte loads in flight per
-        // thread (faster for FP64 than two dword copies per value).
+        // Field stage by global -> LDS loads (global_load_lds, into a wave's
+        // consecutive LDS words at a wave-uniform base held in M0, which on
+        // gfx950 reaches the whole LDS, past 64 KB too): no value passes
+        // through a register, so a thread's loads all stay in flight until
+        // the wait before the barrier below.  Rows aligned to 16 bytes that
+        // need no wrap along x take 16 bytes a lane (4 FP32 or 2 FP64
+        // nodes); other FP32 rows one dword a lane; other FP64 rows go
+        // through registers, STAGE_BATCH 8-byte loads in flight per thread
+        // (faster for FP64 than two dword copies per value).
         const int lane = tid & 63;
-        constexpr bool dma = sizeof(FT) == 4;
+        constexpr int AL = 16 / (int)sizeof(FT);
 #pragma unroll
         for (int c = 0; c < 6; ++c) {
             const FT *srcf = (const FT *)(c < 3 ? prm.f.E[c] : prm.f.B[c - 3]);
-            if constexpr (dma) {
+            // 16 bytes a lane: aligned, unpadded rows that need no wrap
+            // along x, from a 16-byte aligned array and first cell
+            const bool x4 = prm.falign && lf.L0[c] == W[c] && lf.o0[c] >= 0 &&
+                            lf.o0[c] + W[c] <= b.n[0] && (b.n[0] & (AL - 1)) == 0 &&
+                            (b.cell_base & (AL - 1)) == 0 && ((unsigned long long)srcf & 15) == 0;
+            if (x4) {
+                unsigned *dst = (unsigned *)((FT *)smem + lf.off[c]);
+                const int q = W[c] / AL;    // 16-byte chunks per row
+                const int nq = q * FL1[c] * FL2[c];
+                RegionWalk w(tid, bs, q, FL1[c], FL2[c]);
+                for (int id = tid; id < nq; id += bs, w.next()) {
+                    int gj = lf.o1[c] + w.j, gk = lf.o2[c] + w.k;
+                    if (any) { gj = wrap_index_any(gj, b.n[1]); gk = wrap_index_any(gk, b.n[2]); }
+                    else { gj = wrap_index(gj, b.n[1]); gk = wrap_index(gk, b.n[2]); }
+                    const long long e = b.cell_base + lf.o0[c] + AL * w.i +
+                                        (long long)b.n[0] * (gj + (long long)b.n[1] * gk);
+                    __builtin_amdgcn_global_load_lds((const unsigned *)(srcf + e), dst + 4 * (id - lane),
+                                                     16, 0, 0);
+                }
+            } else if constexpr (sizeof(FT) == 4) {
                 unsigned *dst = (unsigned *)((FT *)smem + lf.off[c]);
                 const unsigned *src = (const unsigned *)srcf;
-                // 16 bytes a lane: aligned, unpadded rows that need no wrap
-                // along x, from a 16-byte aligned array and first cell
-                const bool x4 = prm.falign && lf.L0[c] == W[c] && lf.o0[c] >= 0 &&
-                                lf.o0[c] + W[c] <= b.n[0] && (b.n[0] & 3) == 0 &&
-                                (b.cell_base & 3) == 0 && ((unsigned long long)srcf & 15) == 0;
-                if (x4) {
-                    const int q = W[c] >> 2;    // 4-node chunks per row
-                    const int nq = q * FL1[c] * FL2[c];
-                    RegionWalk w(tid, bs, q, FL1[c], FL2[c]);
-                    for (int id = tid; id < nq; id += bs, w.next()) {
-                        int gj = lf.o1[c] + w.j, gk = lf.o2[c] + w.k;
-                        if (any) { gj = wrap_index_any(gj, b.n[1]); gk = wrap_index_any(gk, b.n[2]); }
-                        else { gj = wrap_index(gj, b.n[1]); gk = wrap_index(gk, b.n[2]); }
-                        const long long e = b.cell_base + lf.o0[c] + 4 * w.i +
-                                            (long long)b.n[0] * (gj + (long long)b.n[1] * gk);
-                        __builtin_amdgcn_global_load_lds(src + e, dst + 4 * (id - lane), 16, 0, 0);
-                    }
-                } else {
-                    const int nd = lf.L01[c] * FL2[c];
-                    RegionWalk w(tid, bs, lf.L0[c], FL1[c], FL2[c]);
-                    for (int id = tid; id < nd; id += bs, w.next()) {
-                        if (w.i >= W[c]) continue;
-                        int gi = lf.o0[c] + w.i, gj = lf.o1[c] + w.j, gk = lf.o2[c] + w.k;
-                        if (any) { gi = wrap_index_any(gi, b.n[0]); gj = wrap_index_any(gj, b.n[1]); gk = wrap_index_any(gk, b.n[2]); }
-                        else { gi = wrap_index(gi, b.n[0]); gj = wrap_index(gj, b.n[1]); gk = wrap_index(gk, b.n[2]); }
-                        const long long e = b.cell_base + gi + (long long)b.n[0] * (gj + (long long)b.n[1] * gk);
-                        __builtin_amdgcn_global_load_lds(src + e, dst + (id - lane), 4, 0, 0);
-                    }
+                const int nd = lf.L01[c] * FL2[c];
+                RegionWalk w(tid, bs, lf.L0[c], FL1[c], FL2[c]);
+                for (int id = tid; id < nd; id += bs, w.next()) {
+                    if (w.i >= W[c]) continue;
+                    int gi = lf.o0[c] + w.i, gj = lf.o1[c] + w.j, gk = lf.o2[c] + w.k;
+                    if (any) { gi = wrap_index_any(gi, b.n[0]); gj = wrap_index_any(gj, b.n[1]); gk = wrap_index_any(gk, b.n[2]); }
+                    else { gi = wrap_index(gi, b.n[0]); gj = wrap_index(gj, b.n[1]); gk = wrap_index(gk, b.n[2]); }
+                    const long long e = b.cell_base + gi + (long long)b.n[0] * (gj + (long long)b.n[1] * gk);
+                    __builtin_amdgcn_global_load_lds(src + e, dst + (id - lane), 4, 0, 0);
                 }
             } else {
                 // through registers: STAGE_BATCH loads in flight per thread

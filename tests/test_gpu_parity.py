@@ -603,6 +603,31 @@ def test_aligned_field_rows_interior_tiles():
     run.free()
 
 
+@pytest.mark.parametrize("order,n,tile", ((2, (48, 16, 12), (16, 8, 4)), (3, (48, 16, 16), (8, 8, 8))))
+def test_aligned_fp64_field_rows(order, n, tile):
+    """The FP64 plain form's field rows aligned to 2 nodes and copied 16
+    bytes a lane (the tile shapes of the FP64 launch configurations: 16x8x4
+    at order 2, 8x8x8 at order 3): interior tiles need no wrap along x (the
+    16-byte copy), edge tiles wrap (the copy through registers into the
+    same aligned rows); three steps against the oracle, node by node, and
+    the particles."""
+    wl = pi.uniform_box(n, 4, 0.05, 0.3, order, 2700 + order, "cpu", tile=tile,
+                        fields="fourier", species=("e", "i"))
+    Eo, Bo, Jo, sps = _oracle_steps(wl, 3)
+    run = GpuRun(wl, pic.PIC_FP64, kernel=pic.PIC_KERNEL_TILED, lane_stride=4, cell_order=-1,
+                 chunk=8192, block=512)
+    run.sort()
+    for _ in range(3):
+        run.particles()
+        pic.pic_fdtd_step(run.ctx, run.f)
+    run.check()
+    E, B, J = run.fields_np()
+    for a, b in ((E, Eo), (B, Bo), (J, Jo)):
+        assert rel_l2(a, b) <= TOL64 and node_max_rel(a, b) <= TOL64, (rel_l2(a, b), node_max_rel(a, b))
+    _compare_state(run, sps, wl.boxes[0], TOL64, TOL64)
+    run.free()
+
+
 @pytest.mark.parametrize("prec,tol", ((pic.PIC_FP64, TOL64), (pic.PIC_FP32_SPLIT, TOL32)))
 @pytest.mark.parametrize("margin", (0, -1))
 def test_margin_on_some_axes(prec, tol, margin):
